@@ -1,0 +1,235 @@
+/*
+ * stencil.h -- C ABI of libstencil.so, an MI355X (gfx950) implementation of
+ * the time-iterated star-stencil sweep of "A shared compilation stack for
+ * distributed-memory parallelism in stencil DSLs" (ASPLOS'24, arXiv 2404.02218).
+ *
+ * Semantics follow the paper's stencil dialect (Section 4.1):
+ *   - a field is a memory buffer whose bounds include the halo (stencil.field);
+ *   - one sweep loads the field (stencil.load), evaluates the update at every
+ *     interior point reading neighbours at constant offsets (stencil.apply /
+ *     stencil.access / stencil.return) and stores the result on a bounded range
+ *     (stencil.store); a sweep never reads what it writes at an offset;
+ *   - the halo is at least as wide as the largest access offset (Section 4.1,
+ *     minimal-halo inference; Figure "stencil_intro": halo points are read-only).
+ * Halo exchanges follow the dmp dialect's declarative exchange (Section 4.2).
+ *
+ * The update bodies (weights c_0..c_r of a centred star of radius r, D axes):
+ *   (L u)_i = D c_0 u_i + sum_d sum_{k=1..r} c_k (u_{i+k e_d} + u_{i-k e_d})
+ *   heat  (Section 5.1, Devito heat listing):  u^{n+1} = u^n + L u^n
+ *         (the caller folds a dt / h^2 into the weights)
+ *   wave  (Section 6.1, second order in time):
+ *         u^{n+1} = 2 u^n - u^{n-1} + beta .* L u^n,  beta = (dt v / h)^2
+ *
+ * Conventions for every entry point:
+ *   - Return value: STENCIL_OK (0) or a negative stencil_status.  On error no
+ *     device work has been enqueued and no caller memory has been touched;
+ *     stencil_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).  No C++ exception crosses the ABI.
+ *   - All device pointers are HIP device allocations owned by the caller.
+ *     The library only enqueues work on the caller's stream (a hipStream_t
+ *     passed as void*; NULL = the legacy default stream); STENCIL_OK means
+ *     "enqueued", not "finished".
+ *   - Arrays of shapes, coordinates and exchange declarations are host
+ *     memory, C order (slowest axis first), and only the first ndim slots of
+ *     a [3] array are read.
+ *   - Compute is FP32 for every storage dtype; 16-bit storage is rounded to
+ *     nearest even.  Source injection and receiver sampling are FP64.
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STENCIL_OK = 0,
+    STENCIL_E_INVALID = -1,     /* bad argument (shape, radius, pointer, box, position) */
+    STENCIL_E_UNSUPPORTED = -2, /* valid but not implemented (e.g. ndim 4) */
+    STENCIL_E_NOMEM = -3,       /* host or device allocation failed, or size overflow */
+    STENCIL_E_DEVICE = -4,      /* a HIP call failed; message holds hipGetErrorString */
+    STENCIL_E_STATE = -5        /* call not valid for this plan (kind, dtype, workspace) */
+} stencil_status;
+
+typedef enum { STENCIL_HEAT = 0, STENCIL_WAVE2 = 1 } stencil_kind;
+typedef enum { STENCIL_F32 = 0, STENCIL_BF16 = 1, STENCIL_F16 = 2 } stencil_dtype;
+typedef enum { STENCIL_BC_DIRICHLET0 = 0, STENCIL_BC_PERIODIC = 1 } stencil_bc;
+
+typedef struct stencil_plan_s* stencil_plan;
+
+/* One dmp.exchange declaration (Section 4.2, listing "halo-swap-op" and figure
+ * "exchange_decl"): receive into buffer box [at, at+size); the box sent to the
+ * rank at relative offset `to` is [at+src_offset, at+src_offset+size).
+ * Coordinates are buffer coordinates (halo included). */
+typedef struct {
+    int64_t at[3];
+    int64_t size[3];
+    int64_t src_offset[3];
+    int32_t to[3];
+    int32_t reserved;
+} stencil_exchange;
+
+/* Point sources: after the sweep of step t, u^{t+1} at pos[s] becomes
+ * round_T(fl64(u^{t+1}) + amp[t*n + s]).  pos: host, [n][3] interior
+ * coordinates.  amp: device FP64, [nsteps][n]. */
+typedef struct {
+    int64_t n;
+    const int64_t* pos;
+    const double* amp;
+} stencil_source;
+
+/* Receivers: trace[t*n + r] = fl64(u^{t+1} at pos[r]) for t = 0..nsteps-1.
+ * pos: host [n][3] interior coordinates.  trace: device FP64 [nsteps][n]. */
+typedef struct {
+    int64_t n;
+    const int64_t* pos;
+    double* trace;
+} stencil_receivers;
+
+/* ---------------------------------------------------------------- plans */
+
+/* Create a plan for fields of interior `shape` (ndim 1..3) with a halo of
+ * `halo` >= `radius` cells on every side of every axis (Section 4.1: the halo
+ * must cover the largest stencil.access offset).  radius 1..4; `coeffs` holds
+ * radius+1 host doubles c_0..c_r (heat: already scaled by a dt/h^2).  The plan
+ * owns small device constants only; it allocates no field memory.
+ * Errors: E_INVALID for ndim/radius/halo/shape out of range or NULL pointers;
+ * E_NOMEM if a field would exceed 2^40 elements. */
+stencil_status stencil_create(stencil_plan* out, stencil_kind kind, int ndim, const int64_t* shape,
+                              int radius, const double* coeffs, int halo, stencil_dtype dtype,
+                              stencil_bc bc);
+
+stencil_status stencil_destroy(stencil_plan plan);
+
+/* Field layout (the stencil.field bounds, Section 4.1), identical for every
+ * field of the plan (u, u_prev, beta).  extents[ndim] = shape + 2*halo;
+ * strides[ndim] in elements; the element at buffer coordinate b is at
+ * base + offset + sum_d b_d * strides[d].  Rows are padded so that the first
+ * interior element of every row is 128-byte aligned.  bytes = allocation size.
+ * Field pointers passed to the library are `base` and must be 256-byte
+ * aligned.  The halo is never written by sweeps (Dirichlet-zero when the
+ * caller zeroes it); with STENCIL_BC_PERIODIC the library refreshes it. */
+stencil_status stencil_layout(stencil_plan plan, int64_t* extents, int64_t* strides,
+                              int64_t* offset, int64_t* bytes);
+
+/* One load/apply/store (Section 4.1) on the interior box [lo, hi) (interior
+ * coordinates, host arrays).  heat: in = {u};  wave: in = {u_n, u_prev, beta}.
+ * `out` must not alias in[0]; for the wave it may alias in[1] (only the
+ * centre of u_prev is read).  Points of `out` outside the box are untouched.
+ * No halo refresh. */
+stencil_status stencil_apply(stencil_plan plan, void* out, const void* const* in,
+                             const int64_t* lo, const int64_t* hi, void* stream);
+
+/* nsteps sweeps of the time loop (Section 5.1: time buffering).
+ *   heat:  fields = {u, u_next}: ping-pong buffers;
+ *   wave:  fields = {u_n, u_prev, beta}: u^{n+1} overwrites u^{n-1} in place.
+ * On return the pointer array is permuted so that fields[0] holds the newest
+ * level (and, for the wave, fields[1] the one before).  With periodic
+ * boundaries the halo of the current level is refreshed before each sweep by
+ * a self-exchange (the dmp.swap of a one-rank periodic grid, Section 4.2).
+ * src/rec may be NULL.  The launches of the run are captured into one HIP
+ * graph per (pointers, nsteps) and replayed. */
+stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
+                           const stencil_receivers* rec, void* stream);
+
+/* ------------------------------------------------------------ exchanges */
+
+/* Exchange declarations of the rank at `coord` of a Cartesian rank grid
+ * `grid` (the decomposition strategy's exchange generator, Section 4.2):
+ * per axis and side with a neighbour, receive the radius-thick halo slab and
+ * send the interior slab next to the same face.  Faces only, no corners (the
+ * star stencil needs none).  A missing neighbour (non-periodic outer face)
+ * produces no exchange, as the paper's lowering uses a null request for it
+ * (Section 4.3).  *n: in = capacity of `out`, out = count (<= 2*ndim). */
+stencil_status stencil_exchanges(stencil_plan plan, const int32_t* grid, const int32_t* coord,
+                                 int periodic, stencil_exchange* out, int* n);
+
+/* Pack the send boxes of n exchanges (host array) from `field` into `buf`
+ * (device), each box in C order, concatenated in declaration order.  The
+ * number of elements is the sum of the box volumes; buf has the field's
+ * storage dtype.  One launch for all boxes. */
+stencil_status stencil_halo_pack(stencil_plan plan, const void* field, const stencil_exchange* ex,
+                                 int n, void* buf, void* stream);
+
+/* Unpack `buf` (as produced by a partner's pack) into the receive boxes. */
+stencil_status stencil_halo_unpack(stencil_plan plan, void* field, const stencil_exchange* ex, int n,
+                                   const void* buf, void* stream);
+
+/* ---------------------------------------------------------- batched shots */
+
+/* A batch of independent wave problems (3D only) of uneven interior shapes
+ * shapes[nshots][3], sharing radius, weights, halo and dtype.  Each shot
+ * has its own fields (layout from stencil_batch_layout). */
+stencil_status stencil_batch_create(stencil_plan* out, int nshots, const int64_t* shapes, int radius,
+                                    const double* coeffs, int halo, stencil_dtype dtype);
+stencil_status stencil_batch_layout(stencil_plan batch, int shot, int64_t* extents, int64_t* strides,
+                                    int64_t* offset, int64_t* bytes);
+
+/* nsteps sweeps of every shot: one launch per step covers the tiles of all
+ * shots, and the nsteps launches are captured into one HIP graph.
+ * fields[3*s + {0,1,2}] = shot s's {u_n, u_prev, beta}, permuted per shot as
+ * in stencil_run.  src / rec: arrays of nshots entries, or NULL. */
+stencil_status stencil_batch_run(stencil_plan batch, void** fields, int64_t nsteps,
+                                 const stencil_source* src, const stencil_receivers* rec, void* stream);
+
+/* ------------------------------------------------------------- adjoint */
+
+/* Workspace bytes for stencil_forward_ckpt / stencil_adjoint (3D wave plans,
+ * FP32 storage): the checkpoints (u^c, u^{c-1}) every checkpoint_every steps,
+ * one segment of second differences, two recompute levels, two adjoint
+ * levels and an FP32 imaging partial. */
+stencil_status stencil_adjoint_workspace(stencil_plan plan, int64_t nsteps, int64_t checkpoint_every,
+                                         size_t* bytes);
+
+/* Forward run as stencil_run (fields = {u_n, u_prev, beta}), also storing
+ * (u^c, u^{c-1}) for c = 0, k, 2k, ... into the workspace. */
+stencil_status stencil_forward_ckpt(stencil_plan plan, void** fields, int64_t nsteps,
+                                    int64_t checkpoint_every, const stencil_source* src,
+                                    const stencil_receivers* rec, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/* Gradient of the data misfit with respect to the squared slowness m
+ * (beta = dt^2 / (h^2 m)), by the exact discrete adjoint of the leapfrog
+ * recurrence: for k = N..1, lam^{k-1} = 2 lam^k - lam^{k+1} + beta .* L lam^k
+ * + rec_scale[r] * resid[(k-1)*nrec + r] at receiver r; and
+ * grad += grad_scale * sum_n lam^n .* (u^{n+1} - 2u^n + u^{n-1}).
+ * The forward levels are recomputed segment by segment from the checkpoints
+ * left in `workspace` by stencil_forward_ckpt with the same nsteps,
+ * checkpoint_every, beta and sources.  For J = 1/2 |d - d_obs|^2:
+ * resid = d - d_obs, rec_scale = dt^2 v_r^2, grad_scale = -1/dt^2.
+ * beta: field layout.  resid, rec_scale: device FP64.  grad: device FP64,
+ * dense interior [nz][ny][nx], accumulated into (not cleared). */
+stencil_status stencil_adjoint(stencil_plan plan, const void* beta, int64_t nsteps,
+                               int64_t checkpoint_every, const stencil_source* src,
+                               const stencil_receivers* rec, const double* resid,
+                               const double* rec_scale, double grad_scale, double* grad,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* beta = dt^2 / (h^2 m) on the interior of a field (halo untouched) from a
+ * dense interior FP64 array m (device), rounded to the plan's dtype. */
+stencil_status stencil_wave_beta(stencil_plan plan, const double* m, double dt, double h, void* beta,
+                                 void* stream);
+
+/* ------------------------------------------------------------ variants */
+
+/* Kernel variants of a plan (tile shape and z-chunk of the 3D sweep; variant
+ * 0 is the one-thread-per-point kernel).  Every variant computes identical
+ * bits.  stencil_tune times the candidates on the caller's fields (reading
+ * them only; outputs go to a scratch field it allocates and frees) and keeps
+ * the fastest; the choice is cached per (kind, ndim, radius, dtype, shape). */
+stencil_status stencil_variant_count(stencil_plan plan, int* count);
+stencil_status stencil_variant_name(stencil_plan plan, int variant, char* buf, size_t len);
+stencil_status stencil_get_variant(stencil_plan plan, int* variant);
+stencil_status stencil_set_variant(stencil_plan plan, int variant);
+stencil_status stencil_tune(stencil_plan plan, void* const* fields, int reps, void* stream);
+
+const char* stencil_last_error(void);
+int stencil_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STENCIL_H */

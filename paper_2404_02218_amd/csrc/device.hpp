@@ -1,0 +1,140 @@
+// Device-side building blocks shared by every sweep kernel: storage types,
+// their FP32 widening / round-to-nearest-even narrowing, and the one
+// per-point arithmetic of the star update.  Every kernel variant evaluates a
+// point with exactly this sequence of operations, so all variants (plain,
+// z-marching, batched, recompute) produce identical bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stn {
+
+// ---------------------------------------------------------------- storage
+struct bf16 {
+    uint16_t bits;
+};
+typedef _Float16 f16;
+
+template <typename T>
+struct Storage;
+
+template <>
+struct Storage<float> {
+    __device__ static inline float load(const float* p) { return *p; }
+    __device__ static inline float to_f(float v) { return v; }
+    __device__ static inline float from_f(float v) { return v; }
+    // four consecutive elements starting at a 16-byte aligned address
+    __device__ static inline float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+    __device__ static inline void store4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+    __device__ static inline void store(float* p, float v) { *p = v; }
+};
+
+// bf16: widening is exact (the 16 bits are the top half of an FP32); narrowing
+// rounds to nearest, ties to even, by adding 0x7FFF plus the lowest kept bit
+// before truncation; NaN stays a quiet NaN.
+__device__ static inline float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ static inline uint16_t f_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <>
+struct Storage<bf16> {
+    __device__ static inline float load(const bf16* p) { return bf16_to_f(p->bits); }
+    __device__ static inline float to_f(bf16 v) { return bf16_to_f(v.bits); }
+    __device__ static inline bf16 from_f(float v) { return bf16{f_to_bf16(v)}; }
+    __device__ static inline float4 load4(const bf16* p) {
+        uint2 r = *reinterpret_cast<const uint2*>(p);
+        return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                           __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+    }
+    __device__ static inline void store4(bf16* p, float4 v) {
+        uint2 r;
+        r.x = (uint32_t)f_to_bf16(v.x) | ((uint32_t)f_to_bf16(v.y) << 16);
+        r.y = (uint32_t)f_to_bf16(v.z) | ((uint32_t)f_to_bf16(v.w) << 16);
+        *reinterpret_cast<uint2*>(p) = r;
+    }
+    __device__ static inline void store(bf16* p, float v) { p->bits = f_to_bf16(v); }
+};
+
+// f16: hardware conversions.  The FP32 value is pinned in a register before
+// narrowing so that the compiler cannot fold the narrowing into the producing
+// FMA (a mixed-precision FMA with an f16 result rounds once instead of twice);
+// every kernel then rounds FP32 -> f16 identically.
+__device__ static inline f16 f_to_f16(float v) {
+    asm volatile("" : "+v"(v));
+    return (f16)v;
+}
+
+template <>
+struct Storage<f16> {
+    __device__ static inline float load(const f16* p) { return (float)(*p); }
+    __device__ static inline float to_f(f16 v) { return (float)v; }
+    __device__ static inline f16 from_f(float v) { return f_to_f16(v); }
+    __device__ static inline float4 load4(const f16* p) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 r = *reinterpret_cast<const h4*>(p);
+        return make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.w);
+    }
+    __device__ static inline void store4(f16* p, float4 v) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 r;
+        r.x = f_to_f16(v.x);
+        r.y = f_to_f16(v.y);
+        r.z = f_to_f16(v.z);
+        r.w = f_to_f16(v.w);
+        *reinterpret_cast<h4*>(p) = r;
+    }
+    __device__ static inline void store(f16* p, float v) { *p = f_to_f16(v); }
+};
+
+// value after a round trip through the storage type
+template <typename T>
+__device__ static inline float through(float v) {
+    return Storage<T>::to_f(Storage<T>::from_f(v));
+}
+
+// ------------------------------------------------------------ coefficients
+struct Coefs {
+    float c[5];  // c_0..c_r (unused tail zero)
+    float cd0;   // D * c_0, the centre weight of the D-axis star
+};
+
+enum Mode : int {
+    MODE_HEAT = 0,      // out = u + L u
+    MODE_WAVE = 1,      // out = 2u - u_prev + beta L u
+    MODE_WAVE_D = 2,    // as MODE_WAVE, also writes beta L u (+ source) to a second-difference field
+    MODE_WAVE_ADJ = 3,  // as MODE_WAVE, then g += out * d for an imaging field pair (g, d)
+};
+
+// Canonical accumulation: centre, then the z pairs, the y pairs, the x pairs,
+// k = 1..r within an axis.  `m[k-1]`, `p[k-1]` are the taps at -k and +k.
+template <int R>
+__device__ static inline float axis_sum(float acc, const Coefs& w, const float* m, const float* p) {
+#pragma unroll
+    for (int k = 1; k <= R; k++) acc = fmaf(w.c[k], m[k - 1] + p[k - 1], acc);
+    return acc;
+}
+
+// the per-point time update given L u (acc), the centre and the previous level
+template <int MODE>
+__device__ static inline float time_update(float acc, float centre, float prev, float beta) {
+    if constexpr (MODE == MODE_HEAT) {
+        return centre + acc;
+    } else {
+        float t = 2.0f * centre - prev;
+        return fmaf(beta, acc, t);
+    }
+}
+
+// source injection: round to storage, widen, add the FP64 amount, round back
+template <typename T>
+__device__ static inline float inject(float v, double amount) {
+    float s = through<T>(v);
+    return (float)((double)s + amount);
+}
+
+}  // namespace stn

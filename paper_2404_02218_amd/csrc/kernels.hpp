@@ -1,0 +1,116 @@
+// Launch descriptors and launcher entry points of the HIP kernels.  The host
+// runtime (runtime.cpp) builds these descriptors after validating every
+// argument, so the kernels themselves trust them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace stn {
+
+enum DType : int { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2 };
+
+inline int dtype_size(int dt) { return dt == DT_F32 ? 4 : 2; }
+
+// Padded field layout shared by every field of a plan.  Internal axes are
+// (z, y, x); inactive leading axes of 1D/2D plans have extent 1 and stride 0.
+struct Grid3 {
+    int nd;          // active axes, 1..3 (the last nd of z, y, x)
+    int n[3];        // interior extents
+    int64_t s[3];    // strides in elements (s[2] == 1)
+    int64_t origin;  // element offset of interior point (0,0,0) from the base
+    int64_t xlead;   // elements from a row's first stored element to its first interior one
+    int64_t rowlen;  // stored elements per row (the x pitch)
+};
+
+// Point sources of one field set.  zyx4 rows are (z, y, x, index) sorted by
+// xy tile of the z-marching kernel, tile_begin is the CSR over tiles; off is
+// the element offset (from the interior origin) of source `index`.
+struct SrcList {
+    int n;
+    const int* zyx4;
+    const int* tile_begin;
+    const int64_t* off;
+    const double* amp;    // [rows][n]; row chosen per launch
+    const double* scale;  // [n] multiplier of amp, or null
+};
+
+struct RecList {
+    int n;
+    const int64_t* off;  // element offsets from the interior origin
+    double* trace;       // [rows][n]
+};
+
+// One field set as the sweep kernels see it.  For in-place wave steps
+// prev == out; a launch with parity 1 swaps the roles of u and prev/out.
+struct ZView {
+    const void* u;
+    const void* prev;   // wave only
+    const void* beta;   // wave only
+    void* out;
+    float* dfield;      // MODE_WAVE_D: written; MODE_WAVE_ADJ: read (same layout)
+    float* gfield;      // MODE_WAVE_ADJ: imaging partial (same layout)
+    Grid3 g;
+    int ntx, nty, zc, nzc;  // z-marching tiling: tiles along x, y; z-chunk length and count
+    SrcList src;
+    RecList rec;
+};
+
+// Tile shapes of the z-marching kernel: BX threads along x with 4 points each,
+// BY thread rows, each thread owning VY rows (strided by BY).
+struct TileCfg {
+    int bx, by, vy;
+};
+inline constexpr TileCfg kTileCfgs[] = {
+    {16, 16, 2},  // 64 x 32 tile, 256 threads
+    {16, 8, 2},   // 64 x 16 tile, 128 threads
+    {32, 8, 2},   // 128 x 16 tile, 256 threads
+    {16, 16, 1},  // 64 x 16 tile, 256 threads
+};
+inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
+// z-chunk lengths of the z-marching variants
+inline constexpr int kZChunks[] = {256, 128, 64, 32};
+inline constexpr int kNumZChunks = sizeof(kZChunks) / sizeof(kZChunks[0]);
+
+inline int tile_tx(int cfg) { return 4 * kTileCfgs[cfg].bx; }
+inline int tile_ty(int cfg) { return kTileCfgs[cfg].by * kTileCfgs[cfg].vy; }
+inline int tile_threads(int cfg) { return kTileCfgs[cfg].bx * kTileCfgs[cfg].by; }
+
+struct Box3 {
+    int64_t lo[3];
+    int64_t n[3];
+};
+
+// up to 6 boxes per launch (the faces of a 3D box)
+struct CopyList {
+    int n;
+    int64_t start[7];
+    int64_t src[6][3];
+    int64_t dst[6][3];
+    int64_t size[6][3];
+};
+
+enum CopyDir : int { COPY_PACK = 0, COPY_UNPACK = 1, COPY_FIELD = 2 };
+
+hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const Coefs& w, const Box3& box,
+                        hipStream_t s);
+hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& v, const Coefs& w,
+                         int parity, int arow, int trow, hipStream_t s);
+hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_start,
+                               int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
+                               hipStream_t s);
+hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s);
+hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecList& rec, int trow,
+                         hipStream_t s);
+hipError_t launch_boxcopy(int dtype, int dir, void* field, const Grid3& g, int64_t offset, const CopyList& L,
+                          void* buf, hipStream_t s);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_beta(int dtype, const double* m, void* beta, const Grid3& g, double scale, hipStream_t s);
+hipError_t launch_flush(float* g32, double* grad, const Grid3& g, double scale, hipStream_t s);
+
+// blocks of one z-marching launch over a field set
+inline int64_t zmarch_blocks(const ZView& v) { return (int64_t)v.ntx * v.nty * v.nzc; }
+
+}  // namespace stn

@@ -1,0 +1,1220 @@
+// Host runtime behind the C ABI of libstencil.so: argument validation, the
+// padded field layout, kernel-variant choice and autotuning, source/receiver
+// tables, HIP-graph capture of time loops, halo exchange declarations, the
+// batched-shot work list and the checkpointed adjoint driver.
+//
+// Every entry point validates all of its arguments before it enqueues any
+// device work; errors are reported through a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "stencil.h"
+
+using namespace stn;
+
+namespace {
+
+thread_local std::string g_err;
+
+stencil_status fail(stencil_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(STENCIL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define ST_TRY(expr)                          \
+    do {                                      \
+        stencil_status s_ = (expr);           \
+        if (s_ != STENCIL_OK) return s_;      \
+    } while (0)
+
+constexpr int64_t kMaxElems = int64_t(1) << 40;
+constexpr int kAlignBytes = 128;  // first interior element of every row
+constexpr int kPtrAlign = 256;    // field base pointers
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    Grid3 g{};
+    int ndim = 0;
+    int halo = 0;
+    int64_t extents[3] = {1, 1, 1};
+    int64_t strides[3] = {0, 0, 0};
+    int64_t offset = 0;
+    int64_t elems = 0;
+    int64_t bytes = 0;
+};
+
+stencil_status make_layout(int ndim, const int64_t* shape, int halo, int dtype, Layout& L) {
+    const int es = dtype_size(dtype);
+    const int64_t A = kAlignBytes / es;
+    L = Layout{};
+    L.ndim = ndim;
+    L.halo = halo;
+    int64_t n3[3] = {1, 1, 1};
+    for (int i = 0; i < ndim; i++) {
+        if (shape[i] < 0) return fail(STENCIL_E_INVALID, "shape entries must be >= 0");
+        if (shape[i] > (int64_t(1) << 30)) return fail(STENCIL_E_NOMEM, "shape entry too large");
+        n3[3 - ndim + i] = shape[i];
+    }
+    const int64_t xlead = round_up(halo, A);
+    const int64_t ex = n3[2] + 2 * halo;
+    const int64_t rowlen = round_up(xlead - halo + ex, A);
+    const int64_t ey = ndim >= 2 ? n3[1] + 2 * halo : 1;
+    const int64_t ez = ndim >= 3 ? n3[0] + 2 * halo : 1;
+    if (ey > kMaxElems / rowlen || ez > kMaxElems / (ey * rowlen))
+        return fail(STENCIL_E_NOMEM, "field would exceed 2^40 elements");
+    L.offset = xlead - halo;
+    int64_t s3[3] = {ndim >= 3 ? ey * rowlen : 0, ndim >= 2 ? rowlen : 0, 1};
+    int64_t e3[3] = {ez, ey, ex};
+    for (int i = 0; i < ndim; i++) {
+        L.extents[i] = e3[3 - ndim + i];
+        L.strides[i] = s3[3 - ndim + i];
+    }
+    L.elems = ez * ey * rowlen + A;
+    L.bytes = L.elems * es;
+    Grid3& g = L.g;
+    g.nd = ndim;
+    for (int a = 0; a < 3; a++) {
+        g.n[a] = (int)n3[a];
+        g.s[a] = s3[a];
+    }
+    const int64_t hz = ndim >= 3 ? halo : 0, hy = ndim >= 2 ? halo : 0;
+    g.origin = L.offset + hz * s3[0] + hy * s3[1] + halo;
+    g.xlead = xlead;
+    g.rowlen = rowlen;
+    return STENCIL_OK;
+}
+
+// device buffer owned by a plan
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    stencil_status ensure(size_t bytes) {
+        if (bytes <= cap) return STENCIL_OK;
+        if (p) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(STENCIL_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        cap = want;
+        return STENCIL_OK;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Upload host bytes to a plan-owned device table.  The table may still be
+// read by work enqueued earlier, so a changed table waits for the device.
+struct DevTable {
+    DevBuf buf;
+    std::vector<char> host;
+    bool valid = false;
+    stencil_status upload(const void* data, size_t bytes) {
+        if (valid && host.size() == bytes && (bytes == 0 || std::memcmp(host.data(), data, bytes) == 0))
+            return STENCIL_OK;
+        if (valid) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+        }
+        ST_TRY(buf.ensure(bytes));
+        if (bytes) {
+            hipError_t e = hipMemcpy(buf.p, data, bytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        host.assign((const char*)data, (const char*)data + bytes);
+        valid = true;
+        return STENCIL_OK;
+    }
+};
+
+struct Variant {
+    bool zmarch = false;
+    int cfg = 0;
+    int zc = 0;
+};
+
+int variant_count_for(int ndim) { return ndim == 3 ? 1 + kNumTileCfgs * kNumZChunks : 1; }
+
+Variant variant_of(int v) {
+    Variant r;
+    if (v <= 0) return r;
+    r.zmarch = true;
+    r.cfg = (v - 1) % kNumTileCfgs;
+    r.zc = kZChunks[(v - 1) / kNumTileCfgs];
+    return r;
+}
+
+// Default z-marching variant: the first tile shape, with the longest z-chunk
+// that still gives at least 4 workgroups per compute unit (256 CUs).
+int default_variant(const Layout& L) {
+    if (L.ndim != 3) return 0;
+    const int cfg = 0;
+    const int64_t ntx = (L.g.n[2] + tile_tx(cfg) - 1) / tile_tx(cfg);
+    const int64_t nty = (L.g.n[1] + tile_ty(cfg) - 1) / tile_ty(cfg);
+    for (int zi = 0; zi < kNumZChunks; zi++) {
+        const int64_t nzc = (L.g.n[0] + kZChunks[zi] - 1) / kZChunks[zi];
+        if (ntx * nty * nzc >= 1024 || zi == kNumZChunks - 1) return 1 + zi * kNumTileCfgs + cfg;
+    }
+    return 1;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+}  // namespace
+
+// One source/receiver table set (positions are host data, validated)
+struct PointTables {
+    DevTable zyx4, tiles, off;
+    int n = 0;
+    int cfg = -1;
+};
+
+struct stencil_plan_s {
+    bool batch = false;
+    int kind = 0, ndim = 0, radius = 0, halo = 0, dtype = 0, bc = 0;
+    int64_t shape[3] = {0, 0, 0};
+    double coeffs[5] = {0, 0, 0, 0, 0};
+    Coefs w{};
+    Layout L;
+    int variant = 0;
+    bool variant_forced = false;
+    PointTables src, rec, adjrec;
+    DevTable periodic_dummy;
+    // graph cache of stencil_run
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
+    // batch
+    std::vector<Layout> shots;
+    std::vector<PointTables> shot_src, shot_rec;
+    DevTable views, block_start;
+    std::vector<int> bstart;
+
+    ~stencil_plan_s() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+stencil_status check_plan(stencil_plan p, bool want_batch) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (p->batch != want_batch)
+        return fail(STENCIL_E_STATE, want_batch ? "not a batch plan" : "batch plan passed to a single-field call");
+    return STENCIL_OK;
+}
+
+stencil_status check_ptr(const void* p, const char* what) {
+    if (!p) return fail(STENCIL_E_INVALID, std::string(what) + " is NULL");
+    if (((uintptr_t)p) % kPtrAlign) return fail(STENCIL_E_INVALID, std::string(what) + " is not 256-byte aligned");
+    return STENCIL_OK;
+}
+
+stencil_status set_coefs(stencil_plan p, int ndim, int radius, const double* coeffs) {
+    if (!coeffs) return fail(STENCIL_E_INVALID, "coeffs is NULL");
+    for (int k = 0; k <= radius; k++)
+        if (!std::isfinite(coeffs[k])) return fail(STENCIL_E_INVALID, "coefficients must be finite");
+    Coefs w{};
+    for (int k = 0; k < 5; k++) w.c[k] = k <= radius ? (float)coeffs[k] : 0.f;
+    w.cd0 = (float)(ndim * coeffs[0]);
+    p->w = w;
+    for (int k = 0; k < 5; k++) p->coeffs[k] = k <= radius ? coeffs[k] : 0.0;
+    return STENCIL_OK;
+}
+
+// validate interior positions (host, [n][3]) against a layout
+stencil_status check_positions(const Layout& L, int64_t n, const int64_t* pos, const char* what) {
+    if (n < 0) return fail(STENCIL_E_INVALID, std::string(what) + ": negative count");
+    if (n > (1 << 24)) return fail(STENCIL_E_INVALID, std::string(what) + ": too many points");
+    if (n > 0 && !pos) return fail(STENCIL_E_INVALID, std::string(what) + ": positions are NULL");
+    for (int64_t i = 0; i < n; i++)
+        for (int d = 0; d < L.ndim; d++) {
+            const int64_t c = pos[3 * i + d];
+            if (c < 0 || c >= L.g.n[3 - L.ndim + d])
+                return fail(STENCIL_E_INVALID, std::string(what) + ": position outside the interior");
+        }
+    return STENCIL_OK;
+}
+
+int64_t interior_offset(const Layout& L, const int64_t* p3) {
+    int64_t off = 0;
+    for (int d = 0; d < L.ndim; d++) off += p3[d] * L.g.s[3 - L.ndim + d];
+    return off;
+}
+
+void zyx_of(const Layout& L, const int64_t* p3, int out[3]) {
+    out[0] = out[1] = out[2] = 0;
+    for (int d = 0; d < L.ndim; d++) out[3 - L.ndim + d] = (int)p3[d];
+}
+
+// Build the device tables of a point list for tile shape `cfg` (CSR over xy
+// tiles for the z-marching kernels; cfg < 0: offsets only).
+stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T) {
+    T.n = (int)n;
+    std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1));
+    for (int64_t i = 0; i < n; i++) off[i] = interior_offset(L, pos + 3 * i);
+    ST_TRY(T.off.upload(off.data(), sizeof(int64_t) * (size_t)n));
+    if (cfg >= 0) {
+        const int TX = tile_tx(cfg), TY = tile_ty(cfg);
+        const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
+        const int nty = std::max(1, (L.g.n[1] + TY - 1) / TY);
+        std::vector<std::pair<int, int>> order((size_t)n);
+        for (int64_t i = 0; i < n; i++) {
+            int zyx[3];
+            zyx_of(L, pos + 3 * i, zyx);
+            order[i] = {(zyx[1] / TY) * ntx + zyx[2] / TX, (int)i};
+        }
+        std::stable_sort(order.begin(), order.end());
+        std::vector<int> zyx4((size_t)std::max<int64_t>(4 * n, 4));
+        std::vector<int> tb((size_t)ntx * nty + 1, 0);
+        for (int64_t k = 0; k < n; k++) {
+            int zyx[3];
+            const int i = order[k].second;
+            zyx_of(L, pos + 3 * i, zyx);
+            zyx4[4 * k + 0] = zyx[0];
+            zyx4[4 * k + 1] = zyx[1];
+            zyx4[4 * k + 2] = zyx[2];
+            zyx4[4 * k + 3] = i;
+            tb[order[k].first + 1]++;
+        }
+        for (size_t t = 1; t < tb.size(); t++) tb[t] += tb[t - 1];
+        ST_TRY(T.zyx4.upload(zyx4.data(), sizeof(int) * (size_t)(4 * n)));
+        ST_TRY(T.tiles.upload(tb.data(), sizeof(int) * tb.size()));
+    }
+    T.cfg = cfg;
+    return STENCIL_OK;
+}
+
+SrcList src_list(const PointTables& T, const double* amp, const double* scale) {
+    SrcList s{};
+    s.n = T.n;
+    s.zyx4 = (const int*)T.zyx4.buf.p;
+    s.tile_begin = (const int*)T.tiles.buf.p;
+    s.off = (const int64_t*)T.off.buf.p;
+    s.amp = amp;
+    s.scale = scale;
+    return s;
+}
+
+RecList rec_list(const PointTables& T, double* trace) {
+    RecList r{};
+    r.n = T.n;
+    r.off = (const int64_t*)T.off.buf.p;
+    r.trace = trace;
+    return r;
+}
+
+void set_tiling(ZView& v, const Layout& L, const Variant& var) {
+    const int TX = tile_tx(var.cfg), TY = tile_ty(var.cfg);
+    v.ntx = (L.g.n[2] + TX - 1) / TX;
+    v.nty = (L.g.n[1] + TY - 1) / TY;
+    v.zc = std::max(1, std::min(var.zc, std::max(1, L.g.n[0])));
+    v.nzc = (L.g.n[0] + v.zc - 1) / v.zc;
+    if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) v.ntx = v.nty = v.nzc = 0;
+}
+
+// Copy list of the periodic self-exchange: each receive box takes the send
+// box of the exchange facing the opposite way (internal z, y, x axes).
+void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out);
+
+stencil_status exchanges_for(const Layout& L, int radius, const int32_t* grid, const int32_t* coord, int periodic,
+                             std::vector<stencil_exchange>& ex) {
+    ex.clear();
+    for (int i = 0; i < L.ndim; i++) {
+        if (grid[i] < 1 || coord[i] < 0 || coord[i] >= grid[i])
+            return fail(STENCIL_E_INVALID, "rank coordinate outside the rank grid");
+    }
+    for (int i = 0; i < L.ndim; i++) {
+        for (int side = 0; side < 2; side++) {
+            const bool has = periodic || (side == 0 ? coord[i] > 0 : coord[i] < grid[i] - 1);
+            if (!has) continue;
+            stencil_exchange e;
+            std::memset(&e, 0, sizeof(e));
+            for (int j = 0; j < L.ndim; j++) {
+                e.at[j] = L.halo;
+                e.size[j] = L.g.n[3 - L.ndim + j];
+            }
+            e.size[i] = radius;
+            if (side == 0) {
+                e.at[i] = L.halo - radius;
+                e.src_offset[i] = radius;
+                e.to[i] = -1;
+            } else {
+                e.at[i] = L.halo + L.g.n[3 - L.ndim + i];
+                e.src_offset[i] = -radius;
+                e.to[i] = 1;
+            }
+            ex.push_back(e);
+        }
+    }
+    return STENCIL_OK;
+}
+
+void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out) {
+    out.clear();
+    int32_t grid[3] = {1, 1, 1}, coord[3] = {0, 0, 0};
+    std::vector<stencil_exchange> ex;
+    exchanges_for(L, radius, grid, coord, 1, ex);
+    CopyList cl{};
+    for (size_t k = 0; k < ex.size(); k++) {
+        size_t partner = k;
+        for (size_t j = 0; j < ex.size(); j++) {
+            bool match = true;
+            for (int i = 0; i < L.ndim; i++) match &= ex[j].to[i] == -ex[k].to[i];
+            if (match) partner = j;
+        }
+        const int b = cl.n;
+        int64_t vol = 1;
+        for (int a = 0; a < 3; a++) {
+            cl.src[b][a] = 0;
+            cl.dst[b][a] = 0;
+            cl.size[b][a] = 1;
+        }
+        for (int i = 0; i < L.ndim; i++) {
+            const int a = 3 - L.ndim + i;
+            cl.src[b][a] = ex[partner].at[i] + ex[partner].src_offset[i];
+            cl.dst[b][a] = ex[k].at[i];
+            cl.size[b][a] = ex[k].size[i];
+            vol *= ex[k].size[i];
+        }
+        cl.start[b + 1] = cl.start[b] + vol;
+        cl.n++;
+    }
+    out.push_back(cl);
+}
+
+// Enqueue nsteps sweeps of a single plan (no capture logic here).
+stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, int64_t nsteps,
+                           const stencil_source* src, const stencil_receivers* rec, hipStream_t s) {
+    const Layout& L = p->L;
+    const Variant var = variant_of(p->variant);
+    const bool wave = p->kind == STENCIL_WAVE2;
+    const int mode = wave ? MODE_WAVE : MODE_HEAT;
+    const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
+    const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    std::vector<CopyList> per;
+    if (p->bc == STENCIL_BC_PERIODIC) periodic_copies(L, p->radius, per);
+    for (int64_t t = 0; t < nsteps; t++) {
+        const int parity = (int)(t & 1);
+        void* cur = parity ? b : a;
+        void* nxt = parity ? a : b;
+        for (const CopyList& cl : per) HIP_TRY(launch_boxcopy(p->dtype, COPY_FIELD, cur, L.g, L.offset, cl, nullptr, s));
+        if (var.zmarch) {
+            ZView v{};
+            v.u = a;
+            v.prev = b;
+            v.out = b;
+            v.beta = beta;
+            v.g = L.g;
+            set_tiling(v, L, var);
+            v.src = sl;
+            v.rec = rl;
+            const int trow = (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1;
+            HIP_TRY(launch_zmarch(mode, p->radius, p->dtype, var.cfg, v, p->w, parity, (int)t, trow, s));
+        } else {
+            ZView v{};
+            v.u = cur;
+            v.prev = nxt;
+            v.out = nxt;
+            v.beta = beta;
+            v.g = L.g;
+            Box3 box{};
+            for (int a3 = 0; a3 < 3; a3++) {
+                box.lo[a3] = 0;
+                box.n[a3] = L.g.n[a3];
+            }
+            HIP_TRY(launch_point(mode, p->radius, p->dtype, v, p->w, box, s));
+            if (sl.n) HIP_TRY(launch_inject(p->dtype, nxt, L.g, sl, (int)t, s));
+            if (rl.n) HIP_TRY(launch_record(p->dtype, nxt, L.g, rl, (int)t, s));
+        }
+    }
+    if (var.zmarch && rl.n > 0 && nsteps > 0) {
+        void* newest = (nsteps & 1) ? b : a;
+        HIP_TRY(launch_record(p->dtype, newest, L.g, rl, (int)(nsteps - 1), s));
+    }
+    return STENCIL_OK;
+}
+
+bool graphs_enabled() {
+    const char* e = std::getenv("STENCIL_NO_GRAPH");
+    return !(e && e[0] && e[0] != '0');
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+extern "C" {
+
+const char* stencil_last_error(void) { return g_err.c_str(); }
+int stencil_abi_version(void) { return 1; }
+
+stencil_status stencil_create(stencil_plan* out, stencil_kind kind, int ndim, const int64_t* shape, int radius,
+                              const double* coeffs, int halo, stencil_dtype dtype, stencil_bc bc) {
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (kind != STENCIL_HEAT && kind != STENCIL_WAVE2) return fail(STENCIL_E_INVALID, "unknown stencil kind");
+    if (ndim < 1 || ndim > 3) return fail(ndim > 3 ? STENCIL_E_UNSUPPORTED : STENCIL_E_INVALID, "ndim must be 1, 2 or 3");
+    if (!shape) return fail(STENCIL_E_INVALID, "shape is NULL");
+    if (radius < 1 || radius > 4) return fail(STENCIL_E_UNSUPPORTED, "radius must be 1..4");
+    if (halo < radius) return fail(STENCIL_E_INVALID, "halo must be >= radius (the largest access offset)");
+    if (halo > 64) return fail(STENCIL_E_INVALID, "halo must be <= 64");
+    if (dtype != STENCIL_F32 && dtype != STENCIL_BF16 && dtype != STENCIL_F16)
+        return fail(STENCIL_E_INVALID, "unknown dtype");
+    if (bc != STENCIL_BC_DIRICHLET0 && bc != STENCIL_BC_PERIODIC) return fail(STENCIL_E_INVALID, "unknown bc");
+    stencil_plan p = new (std::nothrow) stencil_plan_s();
+    if (!p) return fail(STENCIL_E_NOMEM, "out of host memory");
+    p->kind = kind;
+    p->ndim = ndim;
+    p->radius = radius;
+    p->halo = halo;
+    p->dtype = dtype;
+    p->bc = bc;
+    for (int i = 0; i < ndim; i++) p->shape[i] = shape[i];
+    stencil_status st = make_layout(ndim, shape, halo, dtype, p->L);
+    if (st == STENCIL_OK) st = set_coefs(p, ndim, radius, coeffs);
+    if (st == STENCIL_OK && bc == STENCIL_BC_PERIODIC) {
+        for (int i = 0; i < ndim; i++)
+            if (shape[i] < radius) st = fail(STENCIL_E_INVALID, "periodic axes need at least `radius` interior points");
+    }
+    if (st != STENCIL_OK) {
+        delete p;
+        return st;
+    }
+    p->variant = default_variant(p->L);
+    *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_destroy(stencil_plan plan) {
+    if (!plan) return fail(STENCIL_E_INVALID, "plan is NULL");
+    delete plan;
+    return STENCIL_OK;
+}
+
+static stencil_status layout_out(const Layout& L, int64_t* extents, int64_t* strides, int64_t* offset,
+                                 int64_t* bytes) {
+    for (int i = 0; i < L.ndim; i++) {
+        if (extents) extents[i] = L.extents[i];
+        if (strides) strides[i] = L.strides[i];
+    }
+    if (offset) *offset = L.offset;
+    if (bytes) *bytes = L.bytes;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_layout(stencil_plan plan, int64_t* extents, int64_t* strides, int64_t* offset, int64_t* bytes) {
+    ST_TRY(check_plan(plan, false));
+    return layout_out(plan->L, extents, strides, offset, bytes);
+}
+
+stencil_status stencil_apply(stencil_plan p, void* out, const void* const* in, const int64_t* lo, const int64_t* hi,
+                             void* stream) {
+    ST_TRY(check_plan(p, false));
+    if (!in) return fail(STENCIL_E_INVALID, "in is NULL");
+    ST_TRY(check_ptr(out, "out"));
+    ST_TRY(check_ptr(in[0], "in[0]"));
+    const bool wave = p->kind == STENCIL_WAVE2;
+    if (wave) {
+        ST_TRY(check_ptr(in[1], "in[1]"));
+        ST_TRY(check_ptr(in[2], "in[2]"));
+        if (out == in[2]) return fail(STENCIL_E_INVALID, "out must not alias beta");
+    }
+    if (out == in[0]) return fail(STENCIL_E_INVALID, "out must not alias the level read at offsets");
+    if (!lo || !hi) return fail(STENCIL_E_INVALID, "lo/hi are NULL");
+    const Layout& L = p->L;
+    Box3 box{};
+    for (int a = 0; a < 3; a++) {
+        box.lo[a] = 0;
+        box.n[a] = 1;
+    }
+    for (int d = 0; d < L.ndim; d++) {
+        const int a = 3 - L.ndim + d;
+        if (lo[d] < 0 || hi[d] < lo[d] || hi[d] > L.g.n[a])
+            return fail(STENCIL_E_INVALID, "box [lo, hi) must lie inside the interior");
+        box.lo[a] = lo[d];
+        box.n[a] = hi[d] - lo[d];
+    }
+    ZView v{};
+    v.u = in[0];
+    v.prev = wave ? in[1] : nullptr;
+    v.beta = wave ? in[2] : nullptr;
+    v.out = out;
+    v.g = L.g;
+    HIP_TRY(launch_point(wave ? MODE_WAVE : MODE_HEAT, p->radius, p->dtype, v, p->w, box, (hipStream_t)stream));
+    return STENCIL_OK;
+}
+
+static stencil_status run_args(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                               const stencil_receivers* rec) {
+    if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
+    const bool wave = p->kind == STENCIL_WAVE2;
+    ST_TRY(check_ptr(fields[0], "fields[0]"));
+    ST_TRY(check_ptr(fields[1], "fields[1]"));
+    if (fields[0] == fields[1]) return fail(STENCIL_E_INVALID, "fields[0] and fields[1] must differ");
+    if (wave) {
+        ST_TRY(check_ptr(fields[2], "fields[2] (beta)"));
+        if (fields[2] == fields[0] || fields[2] == fields[1]) return fail(STENCIL_E_INVALID, "beta must not alias a level");
+    }
+    if (nsteps < 0) return fail(STENCIL_E_INVALID, "nsteps must be >= 0");
+    if (nsteps > (int64_t(1) << 30)) return fail(STENCIL_E_INVALID, "nsteps too large");
+    if (src && src->n > 0) {
+        ST_TRY(check_positions(p->L, src->n, src->pos, "sources"));
+        if (!src->amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+    }
+    if (rec && rec->n > 0) {
+        ST_TRY(check_positions(p->L, rec->n, rec->pos, "receivers"));
+        if (!rec->trace) return fail(STENCIL_E_INVALID, "receiver trace is NULL");
+    }
+    return STENCIL_OK;
+}
+
+static stencil_status prepare_points(stencil_plan p, const stencil_source* src, const stencil_receivers* rec) {
+    const Variant var = variant_of(p->variant);
+    const int cfg = var.zmarch ? var.cfg : -1;
+    ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, cfg, p->src));
+    ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
+    return STENCIL_OK;
+}
+
+stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                           const stencil_receivers* rec, void* stream) {
+    ST_TRY(check_plan(p, false));
+    ST_TRY(run_args(p, fields, nsteps, src, rec));
+    ST_TRY(prepare_points(p, src, rec));
+    hipStream_t s = (hipStream_t)stream;
+    void* a = fields[0];
+    void* b = fields[1];
+    const void* beta = p->kind == STENCIL_WAVE2 ? fields[2] : nullptr;
+    if (nsteps >= 2 && graphs_enabled()) {
+        std::vector<int64_t> key = {(int64_t)(uintptr_t)a,
+                                    (int64_t)(uintptr_t)b,
+                                    (int64_t)(uintptr_t)beta,
+                                    nsteps,
+                                    p->variant,
+                                    (int64_t)(uintptr_t)(src ? src->amp : nullptr),
+                                    (int64_t)(uintptr_t)(rec ? rec->trace : nullptr),
+                                    (int64_t)(uintptr_t)p->src.off.buf.p,
+                                    (int64_t)(uintptr_t)p->rec.off.buf.p,
+                                    (int64_t)(uintptr_t)p->src.zyx4.buf.p,
+                                    (int64_t)(uintptr_t)p->src.tiles.buf.p,
+                                    p->src.n,
+                                    p->rec.n};
+        if (!p->gexec || key != p->gkey) {
+            if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+            if (p->gexec) {
+                HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(hipGraphExecDestroy(p->gexec));
+                p->gexec = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            stencil_status st = enqueue_run(p, a, b, beta, nsteps, src, rec, p->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap, &graph);
+            if (st != STENCIL_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                p->gexec = nullptr;
+                return fail(STENCIL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            p->gkey = key;
+        }
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+    } else {
+        ST_TRY(enqueue_run(p, a, b, beta, nsteps, src, rec, s));
+    }
+    if (nsteps & 1) std::swap(fields[0], fields[1]);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_exchanges(stencil_plan p, const int32_t* grid, const int32_t* coord, int periodic,
+                                 stencil_exchange* out, int* n) {
+    ST_TRY(check_plan(p, false));
+    if (!grid || !coord || !n) return fail(STENCIL_E_INVALID, "grid, coord and n must be non-NULL");
+    std::vector<stencil_exchange> ex;
+    ST_TRY(exchanges_for(p->L, p->radius, grid, coord, periodic, ex));
+    if (out && *n < (int)ex.size()) return fail(STENCIL_E_INVALID, "capacity of `out` is too small");
+    if (out)
+        for (size_t i = 0; i < ex.size(); i++) out[i] = ex[i];
+    *n = (int)ex.size();
+    return STENCIL_OK;
+}
+
+static stencil_status halo_copy(stencil_plan p, void* field, const stencil_exchange* ex, int n, void* buf,
+                                int dir, void* stream) {
+    ST_TRY(check_plan(p, false));
+    ST_TRY(check_ptr(field, "field"));
+    if (n < 0 || (n > 0 && !ex)) return fail(STENCIL_E_INVALID, "bad exchange list");
+    if (n > 0 && !buf) return fail(STENCIL_E_INVALID, "buf is NULL");
+    const Layout& L = p->L;
+    std::vector<CopyList> lists;
+    CopyList cl{};
+    for (int k = 0; k < n; k++) {
+        int64_t vol = 1;
+        const int b = cl.n;
+        for (int a = 0; a < 3; a++) {
+            cl.src[b][a] = cl.dst[b][a] = 0;
+            cl.size[b][a] = 1;
+        }
+        for (int i = 0; i < L.ndim; i++) {
+            const int a = 3 - L.ndim + i;
+            const int64_t at = ex[k].at[i], sz = ex[k].size[i];
+            const int64_t from = dir == COPY_PACK ? at + ex[k].src_offset[i] : at;
+            if (sz < 0 || from < 0 || from + sz > L.extents[i])
+                return fail(STENCIL_E_INVALID, "exchange box outside the field bounds");
+            cl.src[b][a] = from;
+            cl.dst[b][a] = from;
+            cl.size[b][a] = sz;
+            vol *= sz;
+        }
+        cl.start[b + 1] = cl.start[b] + vol;
+        cl.n++;
+        if (cl.n == 6 || k == n - 1) {
+            lists.push_back(cl);
+            const int64_t carry = cl.start[cl.n];
+            cl = CopyList{};
+            cl.start[0] = carry;
+        }
+    }
+    // each list addresses buf from its own start offset
+    for (CopyList& l : lists) {
+        const int64_t base = l.start[0];
+        for (int b = 0; b <= l.n; b++) l.start[b] -= base;
+        char* bp = (char*)buf + base * dtype_size(p->dtype);
+        HIP_TRY(launch_boxcopy(p->dtype, dir, field, L.g, L.offset, l, bp, (hipStream_t)stream));
+    }
+    return STENCIL_OK;
+}
+
+stencil_status stencil_halo_pack(stencil_plan p, const void* field, const stencil_exchange* ex, int n, void* buf,
+                                 void* stream) {
+    return halo_copy(p, (void*)field, ex, n, buf, COPY_PACK, stream);
+}
+
+stencil_status stencil_halo_unpack(stencil_plan p, void* field, const stencil_exchange* ex, int n, const void* buf,
+                                   void* stream) {
+    return halo_copy(p, field, ex, n, (void*)buf, COPY_UNPACK, stream);
+}
+
+// ------------------------------------------------------------------ batch
+stencil_status stencil_batch_create(stencil_plan* out, int nshots, const int64_t* shapes, int radius,
+                                    const double* coeffs, int halo, stencil_dtype dtype) {
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nshots < 1 || nshots > 4096) return fail(STENCIL_E_INVALID, "nshots must be 1..4096");
+    if (!shapes) return fail(STENCIL_E_INVALID, "shapes is NULL");
+    if (radius != 4) return fail(STENCIL_E_UNSUPPORTED, "batched shots support radius 4 (space order 8)");
+    if (halo < radius || halo > 64) return fail(STENCIL_E_INVALID, "halo must be in [radius, 64]");
+    if (dtype != STENCIL_F32 && dtype != STENCIL_BF16 && dtype != STENCIL_F16)
+        return fail(STENCIL_E_INVALID, "unknown dtype");
+    stencil_plan p = new (std::nothrow) stencil_plan_s();
+    if (!p) return fail(STENCIL_E_NOMEM, "out of host memory");
+    p->batch = true;
+    p->kind = STENCIL_WAVE2;
+    p->ndim = 3;
+    p->radius = radius;
+    p->halo = halo;
+    p->dtype = dtype;
+    stencil_status st = set_coefs(p, 3, radius, coeffs);
+    p->shots.resize(nshots);
+    for (int s = 0; s < nshots && st == STENCIL_OK; s++) st = make_layout(3, shapes + 3 * s, halo, dtype, p->shots[s]);
+    if (st != STENCIL_OK) {
+        delete p;
+        return st;
+    }
+    p->shot_src.resize(nshots);
+    p->shot_rec.resize(nshots);
+    // default: the 64x32 tile with 64-plane chunks
+    p->variant = 1 + 2 * kNumTileCfgs + 0;
+    *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_batch_layout(stencil_plan p, int shot, int64_t* extents, int64_t* strides, int64_t* offset,
+                                    int64_t* bytes) {
+    ST_TRY(check_plan(p, true));
+    if (shot < 0 || shot >= (int)p->shots.size()) return fail(STENCIL_E_INVALID, "shot index out of range");
+    return layout_out(p->shots[shot], extents, strides, offset, bytes);
+}
+
+static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                                    const stencil_receivers* rec, const Variant& var, std::vector<ZView>& views) {
+    const int ns = (int)p->shots.size();
+    views.assign(ns, ZView{});
+    p->bstart.assign(ns + 1, 0);
+    for (int s = 0; s < ns; s++) {
+        const Layout& L = p->shots[s];
+        ZView& v = views[s];
+        v.u = fields[3 * s];
+        v.prev = fields[3 * s + 1];
+        v.out = fields[3 * s + 1];
+        v.beta = fields[3 * s + 2];
+        v.g = L.g;
+        set_tiling(v, L, var);
+        const stencil_source* ss = src ? &src[s] : nullptr;
+        const stencil_receivers* rr = rec ? &rec[s] : nullptr;
+        ST_TRY(build_points(L, ss ? ss->n : 0, ss ? ss->pos : nullptr, var.cfg, p->shot_src[s]));
+        ST_TRY(build_points(L, rr ? rr->n : 0, rr ? rr->pos : nullptr, -1, p->shot_rec[s]));
+        v.src = src_list(p->shot_src[s], ss ? ss->amp : nullptr, nullptr);
+        v.rec = rec_list(p->shot_rec[s], rr ? rr->trace : nullptr);
+        const int64_t nb = zmarch_blocks(v);
+        if ((int64_t)p->bstart[s] + nb > (int64_t(1) << 30)) return fail(STENCIL_E_INVALID, "batch too large");
+        p->bstart[s + 1] = p->bstart[s] + (int)nb;
+    }
+    (void)nsteps;
+    ST_TRY(p->views.upload(views.data(), sizeof(ZView) * views.size()));
+    ST_TRY(p->block_start.upload(p->bstart.data(), sizeof(int) * p->bstart.size()));
+    return STENCIL_OK;
+}
+
+static stencil_status enqueue_batch(stencil_plan p, const std::vector<ZView>& views, int64_t nsteps, const Variant& var,
+                                    bool any_rec, hipStream_t s) {
+    const int ns = (int)p->shots.size();
+    const int nblocks = p->bstart[ns];
+    for (int64_t t = 0; t < nsteps; t++) {
+        const int trow = (any_rec && t >= 1) ? (int)(t - 1) : -1;
+        HIP_TRY(launch_zmarch_batch(p->radius, p->dtype, var.cfg, (const ZView*)p->views.buf.p,
+                                    (const int*)p->block_start.buf.p, ns, nblocks, p->w, (int)(t & 1), (int)t, trow, s));
+    }
+    if (any_rec && nsteps > 0) {
+        for (int sh = 0; sh < ns; sh++) {
+            const ZView& v = views[sh];
+            if (v.rec.n == 0) continue;
+            const void* newest = (nsteps & 1) ? v.prev : v.u;
+            HIP_TRY(launch_record(p->dtype, newest, v.g, v.rec, (int)(nsteps - 1), s));
+        }
+    }
+    return STENCIL_OK;
+}
+
+stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                                 const stencil_receivers* rec, void* stream) {
+    ST_TRY(check_plan(p, true));
+    if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
+    if (nsteps < 0 || nsteps > (int64_t(1) << 30)) return fail(STENCIL_E_INVALID, "bad nsteps");
+    const int ns = (int)p->shots.size();
+    bool any_rec = false;
+    for (int s = 0; s < ns; s++) {
+        for (int k = 0; k < 3; k++) ST_TRY(check_ptr(fields[3 * s + k], "shot field"));
+        if (fields[3 * s] == fields[3 * s + 1] || fields[3 * s + 2] == fields[3 * s] || fields[3 * s + 2] == fields[3 * s + 1])
+            return fail(STENCIL_E_INVALID, "a shot's fields must be distinct");
+        if (src && src[s].n > 0) {
+            ST_TRY(check_positions(p->shots[s], src[s].n, src[s].pos, "sources"));
+            if (!src[s].amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+        }
+        if (rec && rec[s].n > 0) {
+            ST_TRY(check_positions(p->shots[s], rec[s].n, rec[s].pos, "receivers"));
+            if (!rec[s].trace) return fail(STENCIL_E_INVALID, "receiver trace is NULL");
+            any_rec = true;
+        }
+    }
+    const Variant var = variant_of(p->variant);
+    std::vector<ZView> views;
+    ST_TRY(batch_prepare(p, fields, nsteps, src, rec, var, views));
+    hipStream_t s = (hipStream_t)stream;
+    if (nsteps >= 2 && graphs_enabled()) {
+        std::vector<int64_t> key = {nsteps, p->variant, (int64_t)(uintptr_t)p->views.buf.p, any_rec};
+        for (const ZView& v : views) {
+            key.push_back((int64_t)(uintptr_t)v.u);
+            key.push_back((int64_t)(uintptr_t)v.prev);
+            key.push_back((int64_t)(uintptr_t)v.beta);
+            key.push_back((int64_t)(uintptr_t)v.src.amp);
+            key.push_back((int64_t)(uintptr_t)v.rec.trace);
+            key.push_back(v.src.n);
+            key.push_back(v.rec.n);
+            key.push_back((int64_t)(uintptr_t)v.src.zyx4);
+            key.push_back((int64_t)(uintptr_t)v.src.tile_begin);
+            key.push_back((int64_t)(uintptr_t)v.rec.off);
+        }
+        if (!p->gexec || key != p->gkey) {
+            if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+            if (p->gexec) {
+                HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(hipGraphExecDestroy(p->gexec));
+                p->gexec = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            stencil_status st = enqueue_batch(p, views, nsteps, var, any_rec, p->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap, &graph);
+            if (st != STENCIL_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                p->gexec = nullptr;
+                return fail(STENCIL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            p->gkey = key;
+        }
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+    } else {
+        ST_TRY(enqueue_batch(p, views, nsteps, var, any_rec, s));
+    }
+    if (nsteps & 1)
+        for (int sh = 0; sh < ns; sh++) std::swap(fields[3 * sh], fields[3 * sh + 1]);
+    return STENCIL_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+struct AdjLayout {
+    int64_t fbytes = 0;  // one field, rounded up to 256 bytes
+    int64_t nseg = 0;
+    int64_t k = 0;
+    // field slot indices
+    int64_t ckpt0 = 0;     // 2*nseg slots
+    int64_t seg0 = 0;      // k slots of second differences
+    int64_t f0 = 0, f1 = 0, l0 = 0, l1 = 0, g = 0;
+    int64_t slots = 0;
+};
+
+static stencil_status adj_layout(stencil_plan p, int64_t nsteps, int64_t k, AdjLayout& A) {
+    if (p->kind != STENCIL_WAVE2 || p->ndim != 3) return fail(STENCIL_E_STATE, "adjoint needs a 3D wave plan");
+    if (p->dtype != STENCIL_F32) return fail(STENCIL_E_STATE, "adjoint needs FP32 storage");
+    if (p->bc != STENCIL_BC_DIRICHLET0) return fail(STENCIL_E_STATE, "adjoint needs the Dirichlet-zero boundary");
+    if (nsteps < 1 || nsteps > (int64_t(1) << 24)) return fail(STENCIL_E_INVALID, "nsteps must be >= 1");
+    if (k < 1 || k > nsteps) return fail(STENCIL_E_INVALID, "checkpoint_every must be in [1, nsteps]");
+    A.fbytes = round_up(p->L.bytes, 256);
+    A.k = k;
+    A.nseg = (nsteps + k - 1) / k;
+    A.ckpt0 = 0;
+    A.seg0 = 2 * A.nseg;
+    A.f0 = A.seg0 + k;
+    A.f1 = A.f0 + 1;
+    A.l0 = A.f1 + 1;
+    A.l1 = A.l0 + 1;
+    A.g = A.l1 + 1;
+    A.slots = A.g + 1;
+    return STENCIL_OK;
+}
+
+static char* slot(void* ws, const AdjLayout& A, int64_t i) { return (char*)ws + i * A.fbytes; }
+
+stencil_status stencil_adjoint_workspace(stencil_plan p, int64_t nsteps, int64_t k, size_t* bytes) {
+    ST_TRY(check_plan(p, false));
+    if (!bytes) return fail(STENCIL_E_INVALID, "bytes is NULL");
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    *bytes = (size_t)(A.slots * A.fbytes);
+    return STENCIL_OK;
+}
+
+static Variant adjoint_variant(stencil_plan p) {
+    Variant var = variant_of(p->variant);
+    if (!var.zmarch) var = variant_of(default_variant(p->L));
+    return var;
+}
+
+stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nsteps, int64_t k, const stencil_source* src,
+                                    const stencil_receivers* rec, void* ws, size_t ws_bytes, void* stream) {
+    ST_TRY(check_plan(p, false));
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    ST_TRY(run_args(p, fields, nsteps, src, rec));
+    ST_TRY(check_ptr(ws, "workspace"));
+    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+    const Variant var = adjoint_variant(p);
+    ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src));
+    ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
+    hipStream_t s = (hipStream_t)stream;
+    const Layout& L = p->L;
+    void* a = fields[0];
+    void* b = fields[1];
+    const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
+    const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    for (int64_t t = 0; t < nsteps; t++) {
+        const int parity = (int)(t & 1);
+        if (t % k == 0) {
+            const int64_t c = t / k;
+            HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 2 * c), parity ? b : a, L.bytes, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 2 * c + 1), parity ? a : b, L.bytes, hipMemcpyDeviceToDevice, s));
+        }
+        ZView v{};
+        v.u = a;
+        v.prev = b;
+        v.out = b;
+        v.beta = fields[2];
+        v.g = L.g;
+        set_tiling(v, L, var);
+        v.src = sl;
+        v.rec = rl;
+        HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, parity, (int)t,
+                              (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1, s));
+    }
+    if (rl.n > 0) HIP_TRY(launch_record(p->dtype, (nsteps & 1) ? b : a, L.g, rl, (int)(nsteps - 1), s));
+    if (nsteps & 1) std::swap(fields[0], fields[1]);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps, int64_t k, const stencil_source* src,
+                               const stencil_receivers* rec, const double* resid, const double* rec_scale,
+                               double grad_scale, double* grad, void* ws, size_t ws_bytes, void* stream) {
+    ST_TRY(check_plan(p, false));
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    ST_TRY(check_ptr(beta, "beta"));
+    ST_TRY(check_ptr(ws, "workspace"));
+    if (!grad) return fail(STENCIL_E_INVALID, "grad is NULL");
+    if (!std::isfinite(grad_scale)) return fail(STENCIL_E_INVALID, "grad_scale must be finite");
+    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+    if (src && src->n > 0) {
+        ST_TRY(check_positions(p->L, src->n, src->pos, "sources"));
+        if (!src->amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+    }
+    const int64_t nrec = rec ? rec->n : 0;
+    if (nrec > 0) {
+        ST_TRY(check_positions(p->L, rec->n, rec->pos, "receivers"));
+        if (!resid || !rec_scale) return fail(STENCIL_E_INVALID, "resid and rec_scale are required with receivers");
+    }
+    const Variant var = adjoint_variant(p);
+    ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src));
+    ST_TRY(build_points(p->L, nrec, nrec ? rec->pos : nullptr, var.cfg, p->adjrec));
+    hipStream_t s = (hipStream_t)stream;
+    const Layout& L = p->L;
+    const SrcList fsrc = src_list(p->src, src ? src->amp : nullptr, nullptr);
+    const SrcList asrc = src_list(p->adjrec, resid, rec_scale);
+    void* F0 = slot(ws, A, A.f0);
+    void* F1 = slot(ws, A, A.f1);
+    void* L0 = slot(ws, A, A.l0);
+    void* L1 = slot(ws, A, A.l1);
+    float* G = (float*)slot(ws, A, A.g);
+    HIP_TRY(launch_zero(L0, L.bytes, s));
+    HIP_TRY(launch_zero(L1, L.bytes, s));
+    HIP_TRY(launch_zero(G, L.bytes, s));
+    int64_t j = 0;  // adjoint steps taken (parity of the lambda buffers)
+    for (int64_t sg = A.nseg - 1; sg >= 0; sg--) {
+        const int64_t c = sg * k, ce = std::min(c + k, nsteps);
+        HIP_TRY(hipMemcpyAsync(F0, slot(ws, A, A.ckpt0 + 2 * sg), L.bytes, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(F1, slot(ws, A, A.ckpt0 + 2 * sg + 1), L.bytes, hipMemcpyDeviceToDevice, s));
+        for (int64_t t = c; t < ce; t++) {
+            ZView v{};
+            v.u = F0;
+            v.prev = F1;
+            v.out = F1;
+            v.beta = beta;
+            v.g = L.g;
+            v.dfield = (float*)slot(ws, A, A.seg0 + (t - c));
+            set_tiling(v, L, var);
+            v.src = fsrc;
+            HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, (int)((t - c) & 1), (int)t, -1, s));
+        }
+        for (int64_t kk = ce; kk > c; kk--) {
+            ZView v{};
+            v.u = L0;
+            v.prev = L1;
+            v.out = L1;
+            v.beta = beta;
+            v.g = L.g;
+            v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 1 - c));
+            v.gfield = G;
+            set_tiling(v, L, var);
+            v.src = asrc;
+            HIP_TRY(launch_zmarch(MODE_WAVE_ADJ, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 1), -1, s));
+            j++;
+        }
+        HIP_TRY(launch_flush(G, grad, L.g, grad_scale, s));
+    }
+    return STENCIL_OK;
+}
+
+stencil_status stencil_wave_beta(stencil_plan p, const double* m, double dt, double h, void* beta, void* stream) {
+    ST_TRY(check_plan(p, false));
+    if (p->kind != STENCIL_WAVE2) return fail(STENCIL_E_STATE, "not a wave plan");
+    if (!m) return fail(STENCIL_E_INVALID, "m is NULL");
+    ST_TRY(check_ptr(beta, "beta"));
+    if (!(dt > 0) || !(h > 0) || !std::isfinite(dt) || !std::isfinite(h))
+        return fail(STENCIL_E_INVALID, "dt and h must be positive and finite");
+    HIP_TRY(launch_beta(p->dtype, m, beta, p->L.g, dt * dt / (h * h), (hipStream_t)stream));
+    return STENCIL_OK;
+}
+
+// --------------------------------------------------------------- variants
+stencil_status stencil_variant_count(stencil_plan p, int* count) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (!count) return fail(STENCIL_E_INVALID, "count is NULL");
+    *count = p->batch ? kNumTileCfgs * kNumZChunks + 1 : variant_count_for(p->ndim);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size_t len) {
+    int n = 0;
+    ST_TRY(stencil_variant_count(p, &n));
+    if (variant < 0 || variant >= n) return fail(STENCIL_E_INVALID, "variant out of range");
+    if (!buf || len == 0) return fail(STENCIL_E_INVALID, "buffer is NULL");
+    std::string name;
+    if (variant == 0) {
+        name = "point";
+    } else {
+        const Variant v = variant_of(variant);
+        name = "zmarch_" + std::to_string(tile_tx(v.cfg)) + "x" + std::to_string(tile_ty(v.cfg)) + "_t" +
+               std::to_string(tile_threads(v.cfg)) + "_zc" + std::to_string(v.zc);
+    }
+    std::snprintf(buf, len, "%s", name.c_str());
+    return STENCIL_OK;
+}
+
+stencil_status stencil_get_variant(stencil_plan p, int* variant) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (!variant) return fail(STENCIL_E_INVALID, "variant is NULL");
+    *variant = p->variant;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_set_variant(stencil_plan p, int variant) {
+    int n = 0;
+    ST_TRY(stencil_variant_count(p, &n));
+    if (variant < 0 || variant >= n) return fail(STENCIL_E_INVALID, "variant out of range");
+    if (p->batch && variant == 0) return fail(STENCIL_E_INVALID, "batch plans need a z-marching variant");
+    p->variant = variant;
+    p->variant_forced = true;
+    return STENCIL_OK;
+}
+
+static std::string tune_key(stencil_plan p) {
+    std::string k = std::to_string(p->batch) + ":" + std::to_string(p->kind) + ":" + std::to_string(p->ndim) + ":" +
+                    std::to_string(p->radius) + ":" + std::to_string(p->dtype);
+    if (p->batch) {
+        for (const Layout& L : p->shots)
+            k += ":" + std::to_string(L.g.n[0]) + "x" + std::to_string(L.g.n[1]) + "x" + std::to_string(L.g.n[2]);
+    } else {
+        for (int a = 0; a < 3; a++) k += ":" + std::to_string(p->L.g.n[a]);
+    }
+    return k;
+}
+
+stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void* stream) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
+    if (reps < 1 || reps > 1000) return fail(STENCIL_E_INVALID, "reps must be 1..1000");
+    int nvar = 0;
+    ST_TRY(stencil_variant_count(p, &nvar));
+    const std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            p->variant = it->second;
+            return STENCIL_OK;
+        }
+    }
+    if (nvar <= 1) return STENCIL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool wave = p->kind == STENCIL_WAVE2;
+    const int mode = wave ? MODE_WAVE : MODE_HEAT;
+    // scratch outputs: the caller's fields are only read
+    std::vector<const Layout*> Ls;
+    if (p->batch)
+        for (const Layout& L : p->shots) Ls.push_back(&L);
+    else
+        Ls.push_back(&p->L);
+    const int nf = p->batch ? 3 : (wave ? 3 : 2);
+    for (size_t i = 0; i < Ls.size(); i++)
+        for (int k = 0; k < (p->batch ? 3 : (wave ? 3 : 1)); k++) ST_TRY(check_ptr(fields[i * nf + k], "field"));
+    int64_t scratch_bytes = 0;
+    for (const Layout* L : Ls) scratch_bytes += round_up(L->bytes, 256);
+    void* scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, (size_t)scratch_bytes));
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int best = p->variant;
+    float best_ms = 1e30f;
+    stencil_status st = STENCIL_OK;
+    DevTable vt, bs;
+    for (int var_i = p->batch ? 1 : 0; var_i < nvar && st == STENCIL_OK; var_i++) {
+        const Variant var = variant_of(var_i);
+        std::vector<ZView> views;
+        std::vector<int> bst(1, 0);
+        int64_t off = 0;
+        for (size_t i = 0; i < Ls.size(); i++) {
+            const Layout& L = *Ls[i];
+            ZView v{};
+            v.u = fields[i * nf + 0];
+            v.prev = wave ? fields[i * nf + 1] : nullptr;
+            v.beta = wave ? fields[i * nf + 2] : nullptr;
+            v.out = (char*)scratch + off;
+            off += round_up(L.bytes, 256);
+            v.g = L.g;
+            if (var.zmarch) set_tiling(v, L, var);
+            views.push_back(v);
+            bst.push_back(bst.back() + (int)zmarch_blocks(v));
+        }
+        if (p->batch) {
+            st = vt.upload(views.data(), sizeof(ZView) * views.size());
+            if (st == STENCIL_OK) st = bs.upload(bst.data(), sizeof(int) * bst.size());
+            if (st != STENCIL_OK) break;
+        }
+        auto launch = [&]() -> hipError_t {
+            if (p->batch)
+                return launch_zmarch_batch(p->radius, p->dtype, var.cfg, (const ZView*)vt.buf.p, (const int*)bs.buf.p,
+                                           (int)views.size(), bst.back(), p->w, 0, 0, -1, s);
+            if (var.zmarch) return launch_zmarch(mode, p->radius, p->dtype, var.cfg, views[0], p->w, 0, 0, -1, s);
+            Box3 box{};
+            for (int a = 0; a < 3; a++) {
+                box.lo[a] = 0;
+                box.n[a] = p->L.g.n[a];
+            }
+            return launch_point(mode, p->radius, p->dtype, views[0], p->w, box, s);
+        };
+        hipError_t e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(STENCIL_E_DEVICE, std::string("tuning launch: ") + hipGetErrorString(e));
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = var_i;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (st != STENCIL_OK) return st;
+    p->variant = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return STENCIL_OK;
+}
+
+}  // extern "C"

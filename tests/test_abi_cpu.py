@@ -1,0 +1,191 @@
+"""Host-side checks of the C ABI: the library loads and exports every entry
+point declared in include/stencil.h, arguments are validated before any
+device work, the field layout has the promised alignment, and the exchange
+generator reproduces the paper's declarations.  No GPU needed: none of these
+calls reaches the HIP runtime's device paths."""
+import ctypes as C
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2404_02218_amd as S
+from paper_2404_02218_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "stencil.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(stencil_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_abi.EXPORTS) == names
+    assert lib.stencil_abi_version() == 1
+
+
+def _create(kind=S.WAVE2, shape=(8, 9, 10), radius=4, halo=4, dtype=S.F32, bc=S.BC_DIRICHLET0,
+            coeffs=None):
+    lib = _abi.lib()
+    h = C.c_void_p()
+    sh = (C.c_int64 * 3)(*shape)
+    c = (C.c_double * 5)(*(coeffs or [1.0, 0.5, 0.25, 0.125, 0.0625]))
+    st = lib.stencil_create(C.byref(h), kind, len(shape), sh, radius, c, halo, dtype, bc)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(radius=5, halo=5), -2),
+    (dict(radius=0), -2),
+    (dict(halo=3), -1),
+    (dict(kind=7), -1),
+    (dict(dtype=9), -1),
+    (dict(bc=4), -1),
+    (dict(shape=(4, -1, 3)), -1),
+    (dict(shape=(3, 3, 3), bc=S.BC_PERIODIC), -1),
+    (dict(coeffs=[float("nan"), 1, 1, 1, 1]), -1),
+])
+def test_create_rejects_bad_arguments(kw, status):
+    st, h = _create(**kw)
+    assert st == status
+    assert not h.value
+    assert _abi.lib().stencil_last_error()
+
+
+def test_create_rejects_ndim_4_and_null():
+    lib = _abi.lib()
+    h = C.c_void_p()
+    sh = (C.c_int64 * 4)(4, 4, 4, 4)
+    c = (C.c_double * 5)(1, 1, 1, 1, 1)
+    assert lib.stencil_create(C.byref(h), 0, 4, sh, 1, c, 1, 0, 0) == -2
+    assert lib.stencil_create(C.byref(h), 0, 3, None, 1, c, 1, 0, 0) == -1
+    assert lib.stencil_create(None, 0, 3, sh, 1, c, 1, 0, 0) == -1
+
+
+@pytest.mark.parametrize("dtype,esize", [(S.F32, 4), (S.BF16, 2), (S.F16, 2)])
+@pytest.mark.parametrize("shape,halo", [((512, 512, 512), 4), ((37, 50, 71), 4), ((256, 256), 1),
+                                        ((126,), 1), ((13, 7, 5), 2)])
+def test_layout_alignment_and_bounds(shape, halo, dtype, esize):
+    p = S.Plan(S.HEAT, shape, 1, [-2.0, 1.0], halo=halo, dtype=dtype)
+    L = p.layout
+    nd = len(shape)
+    assert list(L.extents) == [n + 2 * halo for n in shape]
+    assert L.strides[-1] == 1
+    # first interior element of every row is 128-byte aligned
+    first = L.offset + halo * sum(L.strides[:-1]) + halo
+    assert (first * esize) % 128 == 0
+    if nd >= 2:
+        assert (L.strides[-2] * esize) % 128 == 0
+        assert L.strides[-2] >= L.offset + L.extents[-1]
+    last = L.offset + sum((e - 1) * s for e, s in zip(L.extents, L.strides))
+    assert last < L.bytes // esize
+
+
+def test_exchange_generator_matches_paper_example_through_abi():
+    with open(os.path.join(ROOT, "tests", "golden", "dmp_exchange_example.json")) as f:
+        g = json.load(f)
+    p = S.Plan(S.WAVE2, g["interior"], g["radius"], [1, 1, 1, 1, 1], halo=g["halo"])
+    ex = [e.as_dict(2) for e in p.exchanges(g["grid"], [0, 0], periodic=True)]
+    assert [d for d in ex if d["to"][0] == 0] == g["printed_exchanges"]
+    assert len(ex) == 4
+
+
+@pytest.mark.parametrize("grid,coord,periodic", [([2, 2, 2], [0, 1, 1], False),
+                                                 ([1, 3, 2], [0, 1, 0], False),
+                                                 ([1, 1, 1], [0, 0, 0], True),
+                                                 ([3, 1, 4], [2, 0, 3], True)])
+def test_exchange_generator_matches_oracle(grid, coord, periodic):
+    shape, halo, r = [12, 10, 14], 5, 3
+    p = S.Plan(S.HEAT, shape, r, [1, 1, 1, 1], halo=halo)
+    mine = [e.as_dict(3) for e in p.exchanges(grid, coord, periodic)]
+    ref = [e.as_dict(3) for e in oracle.exchanges(shape, halo, r, grid, coord, periodic)]
+    assert mine == ref
+
+
+def test_exchange_generator_rejects_bad_coordinates():
+    p = S.Plan(S.HEAT, [8, 8], 1, [1, 1])
+    with pytest.raises(S.StencilError):
+        p.exchanges([2, 2], [2, 0])
+
+
+def test_product_weights_equal_oracle_derivation():
+    for so in (2, 4, 6, 8):
+        assert S.second_derivative_weights(so) == oracle.fd_weights_float(so)
+
+
+def test_variants_are_listed():
+    p = S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8))
+    n = p.variant_count()
+    assert n == 17
+    names = [p.variant_name(v) for v in range(n)]
+    assert names[0] == "point" and len(set(names)) == n
+    p2 = S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2))
+    assert p2.variant_count() == 1 and p2.variant == 0
+    with pytest.raises(S.StencilError):
+        p.variant = n
+
+
+def test_run_validates_before_any_device_work():
+    p = S.Plan(S.WAVE2, (16, 16, 16), 4, S.second_derivative_weights(8))
+    lib = _abi.lib()
+    fake = (C.c_void_p * 3)(256, 512, 768)
+    # NULL and misaligned pointers
+    assert lib.stencil_run(p.handle, None, 1, None, None, None) == -1
+    bad = (C.c_void_p * 3)(256, 513, 768)
+    assert lib.stencil_run(p.handle, bad, 1, None, None, None) == -1
+    same = (C.c_void_p * 3)(256, 256, 768)
+    assert lib.stencil_run(p.handle, same, 1, None, None, None) == -1
+    assert lib.stencil_run(p.handle, fake, -1, None, None, None) == -1
+    # a source outside the interior
+    pos = np.array([[0, 0, 16]], dtype=np.int64)
+    src = _abi.Source(1, pos.ctypes.data_as(C.c_void_p), C.c_void_p(4096))
+    assert lib.stencil_run(p.handle, fake, 1, C.byref(src), None, None) == -1
+    assert b"outside" in lib.stencil_last_error()
+    # the pointer array is untouched on error
+    assert [fake[i] for i in range(3)] == [256, 512, 768]
+
+
+def test_apply_rejects_boxes_outside_interior():
+    p = S.Plan(S.HEAT, (10, 12), 1, S.heat_weights(2, 0.1))
+    lib = _abi.lib()
+    ins = (C.c_void_p * 3)(256, 0, 0)
+    lo = (C.c_int64 * 3)(0, 0)
+    hi = (C.c_int64 * 3)(11, 12)
+    assert lib.stencil_apply(p.handle, C.c_void_p(512), ins, lo, hi, None) == -1
+    hi2 = (C.c_int64 * 3)(10, 12)
+    assert lib.stencil_apply(p.handle, C.c_void_p(256), ins, lo, hi2, None) == -1  # aliasing
+
+
+def test_adjoint_workspace_and_state_errors():
+    p = S.Plan(S.WAVE2, (20, 20, 20), 4, S.second_derivative_weights(8))
+    b = p.adjoint_workspace_bytes(100, 25)
+    assert b >= (2 * 4 + 25 + 5) * 1  # slots
+    with pytest.raises(S.StencilError):
+        p.adjoint_workspace_bytes(100, 0)
+    h = S.Plan(S.HEAT, (20, 20, 20), 2, S.heat_weights(4, 0.05))
+    with pytest.raises(S.StencilError) as e:
+        h.adjoint_workspace_bytes(10, 5)
+    assert e.value.status == -5
+    p16 = S.Plan(S.WAVE2, (20, 20, 20), 4, S.second_derivative_weights(8), dtype=S.BF16)
+    with pytest.raises(S.StencilError):
+        p16.adjoint_workspace_bytes(10, 5)
+
+
+def test_batch_plan_validation():
+    with pytest.raises(S.StencilError):
+        S.BatchPlan([(10, 10, 10)], 2, S.second_derivative_weights(4))
+    bp = S.BatchPlan([(10, 12, 14), (20, 9, 33)], 4, S.second_derivative_weights(8))
+    assert len(bp.layouts) == 2
+    assert list(bp.layouts[1].extents) == [28, 17, 41]
+    with pytest.raises(S.StencilError):
+        bp.variant = 0

@@ -1,0 +1,110 @@
+"""GPU parity of the checkpointed adjoint: traces, misfit gradient against
+the FP64 oracle's gradient, and the gradient against central differences of
+the GPU misfit."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2404_02218_amd as S
+import workloads as W
+from _helpers import torch_f64
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(shape=(34, 30, 38), steps=110, seed=131):
+    rng = np.random.default_rng(seed)
+    h = 10.0
+    v0 = W.layered_velocity(rng, shape)
+    vt = v0 * (1 + 0.2 * W.gaussian_bump(shape, 6.0))
+    dt = W.wave_dt(max(v0.max(), vt.max()), h)
+    src = np.array([[4, shape[1] // 2, shape[2] // 2]])
+    rec = np.array([[3, shape[1] // 2, x] for x in range(3, shape[2] - 3, 4)])
+    w = W.ricker(np.arange(steps) * dt, f0=40.0)
+    return dict(shape=shape, h=h, dt=dt, v0=v0, vt=vt, src=src, rec=rec, w=w, steps=steps)
+
+
+def _oracle(P, m, dobs):
+    dt, h = P["dt"], P["h"]
+    beta = W.round_to_storage(dt * dt / (h * h * m), "f32")
+    amp = (dt * dt / m[tuple(P["src"][0])] * P["w"]).reshape(-1, 1)
+    rec_w = np.array([dt * dt / m[tuple(p)] for p in P["rec"]])
+    return oracle.wave_gradient(W.embed(beta, 4), 4, 4, oracle.fd_weights_float(8), P["steps"],
+                                P["src"], amp, P["rec"], dobs, rec_w, -1.0 / (dt * dt))
+
+
+def _gpu(P, m, dobs, every, device, want_grad=True):
+    import torch
+    dt, h, steps = P["dt"], P["h"], P["steps"]
+    plan = S.Plan(S.WAVE2, P["shape"], 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    beta = W.round_to_storage(dt * dt / (h * h * m), "f32")
+    f[2].load(W.embed(beta, 4))
+    amp = torch_f64((dt * dt / m[tuple(P["src"][0])] * P["w"]).reshape(-1, 1), device)
+    nrec = len(P["rec"])
+    tr = torch.zeros((steps, nrec), dtype=torch.float64, device=device)
+    ws = torch.empty(plan.adjoint_workspace_bytes(steps, every), dtype=torch.uint8, device=device)
+    plan.forward_ckpt(f, steps, every, ws, src=P["src"], src_amp=amp, rec=P["rec"], rec_trace=tr)
+    d = tr.cpu().numpy()
+    J = 0.5 * float(np.sum((d - dobs) ** 2))
+    if not want_grad:
+        return d, J, None
+    resid = torch_f64(d - dobs, device)
+    scale = torch_f64(np.array([dt * dt / m[tuple(p)] for p in P["rec"]]), device)
+    grad = torch.zeros(P["shape"], dtype=torch.float64, device=device)
+    beta_f = plan.field().load(W.embed(beta, 4))
+    plan.adjoint(beta_f, steps, every, ws, resid, P["rec"], scale, -1.0 / (dt * dt), grad,
+                 src=P["src"], src_amp=amp)
+    torch.cuda.synchronize()
+    return d, J, grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("every", [25, 7, 110])
+def test_gradient_matches_oracle(device, every):
+    P = _problem()
+    nrec = len(P["rec"])
+    dobs, _, _ = _oracle(P, 1 / P["vt"] ** 2, np.zeros((P["steps"], nrec)))
+    m0 = 1 / P["v0"] ** 2
+    rtr, rJ, rg = _oracle(P, m0, dobs)
+    d, J, g = _gpu(P, m0, dobs, every, device)
+    e_d = np.max(np.abs(d - rtr)) / np.max(np.abs(rtr))
+    e_J = abs(J - rJ) / rJ
+    e_g = np.linalg.norm(g - rg) / np.linalg.norm(rg)
+    print(f"checkpoint every {every}: traces {e_d:.2e}, misfit {e_J:.2e}, gradient rel L2 {e_g:.2e}")
+    assert e_d <= 1e-5
+    # J and g are driven by residuals d - d_obs, much smaller than d itself, so
+    # the FP32 trace error (<= 1e-5 of max|d|) is amplified by max|d| / |d - d_obs|
+    assert e_J <= 5e-3
+    assert e_g <= 1e-3
+
+
+def test_gradient_matches_gpu_central_differences(device):
+    P = _problem(shape=(30, 28, 32), steps=90, seed=137)
+    nrec = len(P["rec"])
+    dobs, _, _ = _oracle(P, 1 / P["vt"] ** 2, np.zeros((P["steps"], nrec)))
+    m0 = 1 / P["v0"] ** 2
+    _, J0, g = _gpu(P, m0, dobs, 25, device)
+    dm = (1 / P["vt"] ** 2 - m0)
+    gdm = float(np.sum(g * dm))
+    eps = 1e-2
+    _, Jp, _ = _gpu(P, m0 + eps * dm, dobs, 25, device, want_grad=False)
+    _, Jm, _ = _gpu(P, m0 - eps * dm, dobs, 25, device, want_grad=False)
+    fd = (Jp - Jm) / (2 * eps)
+    print(f"J0 {J0:.6e}  FD {fd:.6e}  <g,dm> {gdm:.6e}")
+    assert abs(fd - gdm) <= 1e-2 * abs(gdm)
+
+
+def test_recompute_equals_forward_bitwise(device):
+    """Checkpointed forward + adjoint with lambda driven by zero residuals
+    leaves the gradient exactly zero, and splitting the forward into
+    checkpoints does not change its traces."""
+    import torch
+    P = _problem(shape=(24, 20, 36), steps=40, seed=139)
+    m0 = 1 / P["v0"] ** 2
+    nrec = len(P["rec"])
+    d1, _, _ = _gpu(P, m0, np.zeros((P["steps"], nrec)), 40, device, want_grad=False)
+    d2, _, _ = _gpu(P, m0, np.zeros((P["steps"], nrec)), 3, device, want_grad=False)
+    assert np.array_equal(d1, d2)
+    _, _, g = _gpu(P, m0, d1, 6, device)
+    assert np.all(g == 0.0)
+    del torch

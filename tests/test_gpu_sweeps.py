@@ -1,0 +1,209 @@
+"""GPU parity of the heat and wave sweeps against the FP64 oracle, through
+the C ABI, plus the bit-exact invariants that need no oracle (every kernel
+variant computes the same bits; run(a)+run(b) == run(a+b); the light cone;
+the halo is never written)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2404_02218_amd as S
+import workloads as W
+from _helpers import gpu_heat, gpu_wave, oracle_wave, rel_err, wave_inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+def test_c1_heat2d_so2_full_size(device):
+    P = W.heat2d_c1()
+    u0 = W.round_to_storage(P.u0, "f32")
+    plan = S.Plan(S.HEAT, P.shape, 1, S.heat_weights(2, P.alpha), halo=1)
+    got = gpu_heat(plan, u0, P.nsteps)
+    c = [P.alpha * x for x in oracle.fd_weights_float(2)]
+    ref = W.interior_of(oracle.heat_run(W.embed(u0, 1), 1, 1, c, P.nsteps), 1)
+    assert rel_err(got, ref) <= TOL_F32
+
+
+def test_heat2d_dirichlet_sine_mode_closed_form(device):
+    n, alpha, steps, p, q = 61, 0.2, 50, 2, 7
+    i = np.arange(1, n + 1)
+    mode = np.outer(np.sin(math.pi * p * i / (n + 1)), np.sin(math.pi * q * i / (n + 1)))
+    g = 1 - 4 * alpha * (math.sin(math.pi * p / (2 * (n + 1))) ** 2
+                         + math.sin(math.pi * q / (2 * (n + 1))) ** 2)
+    plan = S.Plan(S.HEAT, (n, n), 1, S.heat_weights(2, alpha), halo=1)
+    got = gpu_heat(plan, W.round_to_storage(mode, "f32"), steps)
+    assert np.max(np.abs(got - g ** steps * mode)) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(37, 45, 83), (70, 33, 130), (1, 1, 1), (5, 64, 64)])
+def test_heat3d_so4_all_variants_bitwise_and_parity(device, shape):
+    rng = np.random.default_rng(21)
+    u0 = W.round_to_storage(rng.random(shape) + W.gaussian_bump(shape, 6.0), "f32")
+    plan = S.Plan(S.HEAT, shape, 2, S.heat_weights(4, 0.05), halo=2)
+    base = gpu_heat(plan, u0, 12, variant=0)
+    c = [0.05 * x for x in oracle.fd_weights_float(4)]
+    ref = W.interior_of(oracle.heat_run(W.embed(u0, 2), 2, 2, c, 12), 2)
+    assert rel_err(base, ref) <= TOL_F32
+    for v in range(1, plan.variant_count()):
+        got = gpu_heat(plan, u0, 12, variant=v)
+        assert np.array_equal(got, base), plan.variant_name(v)
+
+
+def test_heat3d_periodic_fourier_mode(device):
+    shape, alpha, steps = (24, 20, 36), 0.05, 30
+    m = (1, 2, 3)
+    k = [2 * math.pi * m[d] / shape[d] for d in range(3)]
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    mode = W.round_to_storage(np.cos(k[0] * z + k[1] * y + k[2] * x + 0.3), "f32")
+    c4 = oracle.fd_weights(4)
+    g = 1 - alpha * sum(oracle.symbol(c4, kd) for kd in k)
+    plan = S.Plan(S.HEAT, shape, 2, S.heat_weights(4, alpha), halo=2, bc=S.BC_PERIODIC)
+    got = gpu_heat(plan, mode, steps)
+    assert np.max(np.abs(got - g ** steps * mode)) <= 2e-6
+    ref = W.interior_of(oracle.heat_run(W.embed(mode, 2), 2, 2,
+                                        [alpha * float(v) for v in c4], steps, periodic=True), 2)
+    assert rel_err(got, ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("shape", [(40, 52, 75), (33, 17, 140)])
+def test_wave3d_so8_parity_with_source_and_receivers(device, shape):
+    u0, um1, beta = wave_inputs(shape, seed=31)
+    src = np.array([[shape[0] // 2, shape[1] // 3, shape[2] - 3], [4, 5, 6]])
+    rec = np.array([[1, 1, 1], [shape[0] - 1, shape[1] - 1, shape[2] - 1], [10, 7, 64 % shape[2]],
+                    [shape[0] // 2, shape[1] // 3, shape[2] - 3]])
+    steps = 60
+    amp = np.random.default_rng(32).standard_normal((steps, 2))
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    a, b, tr = gpu_wave(plan, u0, um1, beta, steps, src=src, amp=amp, rec=rec)
+    ra, rb, rtr = oracle_wave(u0, um1, beta, 4, 4, steps, src=src, amp=amp, rec=rec)
+    assert rel_err(a, ra) <= TOL_F32
+    assert rel_err(b, rb) <= TOL_F32
+    assert rel_err(tr, rtr) <= TOL_F32
+
+
+def test_wave3d_all_variants_bitwise(device):
+    shape = (45, 38, 97)
+    u0, um1, beta = wave_inputs(shape, seed=41)
+    src = np.array([[20, 30, 90], [44, 0, 0]])
+    rec = np.array([[20, 30, 90], [3, 3, 3]])
+    amp = np.random.default_rng(42).standard_normal((9, 2))
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    base = gpu_wave(plan, u0, um1, beta, 9, src=src, amp=amp, rec=rec, variant=0)
+    for v in range(1, plan.variant_count()):
+        got = gpu_wave(plan, u0, um1, beta, 9, src=src, amp=amp, rec=rec, variant=v)
+        for x, y in zip(got, base):
+            assert np.array_equal(x, y), plan.variant_name(v)
+
+
+def test_wave_split_runs_are_bitwise_equal(device):
+    shape = (30, 41, 66)
+    u0, um1, beta = wave_inputs(shape, seed=51)
+    src = np.array([[15, 20, 33]])
+    rec = np.array([[15, 20, 40], [2, 2, 2]])
+    amp = np.random.default_rng(52).standard_normal((23, 1))
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    whole = gpu_wave(plan, u0, um1, beta, 23, src=src, amp=amp, rec=rec)
+    parts = gpu_wave(plan, u0, um1, beta, 23, src=src, amp=amp, rec=rec, split=[7, 1, 15])
+    for x, y in zip(whole, parts):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("steps", [1, 4, 9])
+def test_wave_light_cone_exact_on_gpu(device, steps):
+    shape, r = (40, 36, 70), 4
+    s = np.array([19, 17, 20])
+    beta = W.round_to_storage(np.random.default_rng(3).uniform(0.01, 0.05, shape), "f32")
+    amp = np.ones((steps, 1))
+    plan = S.Plan(S.WAVE2, shape, r, S.second_derivative_weights(8), halo=r)
+    z0 = np.zeros(shape)
+    a, _, _ = gpu_wave(plan, z0, z0, beta, steps, src=[s], amp=amp)
+    zz, yy, xx = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    hops = (np.ceil(np.abs(zz - s[0]) / r) + np.ceil(np.abs(yy - s[1]) / r)
+            + np.ceil(np.abs(xx - s[2]) / r))
+    assert np.all(a[hops > steps - 1] == 0.0)
+    tip = s.copy()
+    tip[2] += r * (steps - 1)
+    assert a[tuple(tip)] != 0.0
+
+
+def test_halo_is_never_written(device):
+    import torch
+    shape = (20, 24, 40)
+    u0, um1, beta = wave_inputs(shape, seed=61)
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    for fld, arr in zip(f, (u0, um1, beta)):
+        full = np.full(tuple(n + 8 for n in shape), np.nan)
+        full[4:-4, 4:-4, 4:-4] = arr
+        # NaN everywhere outside the star's reach: corners and edges of the halo
+        ring = W.embed(np.ones(shape), 4)
+        for d in range(3):
+            sl = [slice(4, -4)] * 3
+            sl[d] = slice(None)
+            ring[tuple(sl)] = 1
+        full[ring == 0] = np.nan
+        # the face halo itself is zero (Dirichlet)
+        face = (ring == 1) & np.isnan(full)
+        full[face] = 0.0
+        fld.load(full)
+    for v in range(plan.variant_count()):
+        plan.variant = v
+        g = [plan.field() for _ in range(3)]
+        for src_f, dst_f in zip(f, g):
+            dst_f.storage.copy_(src_f.storage)
+        before = g[1].to_numpy()
+        plan.run(g, 3)
+        torch.cuda.synchronize()
+        out = g[0].to_numpy()
+        assert np.all(np.isfinite(out[4:-4, 4:-4, 4:-4])), plan.variant_name(v)
+        halo_mask = np.ones(out.shape, bool)
+        halo_mask[4:-4, 4:-4, 4:-4] = False
+        np.testing.assert_array_equal(out[halo_mask], before[halo_mask])
+
+
+@pytest.mark.parametrize("shape,so", [((300,), 8), ((57, 91), 4), ((64, 129), 8)])
+def test_wave_1d_2d_parity(device, shape, so):
+    r = so // 2
+    u0, um1, beta = wave_inputs(shape, seed=71, halo=r)
+    src = np.array([[s // 2 for s in shape]])
+    rec = np.array([[s // 3 for s in shape]])
+    amp = np.random.default_rng(72).standard_normal((40, 1))
+    plan = S.Plan(S.WAVE2, shape, r, S.second_derivative_weights(so), halo=r)
+    a, b, tr = gpu_wave(plan, u0, um1, beta, 40, src=src, amp=amp, rec=rec)
+    ra, rb, rtr = oracle_wave(u0, um1, beta, r, r, 40, src=src, amp=amp, rec=rec)
+    assert rel_err(a, ra) <= TOL_F32 and rel_err(tr, rtr) <= TOL_F32
+
+
+def test_apply_on_sub_box(device):
+    import torch
+    shape = (21, 30, 45)
+    u0, um1, beta = wave_inputs(shape, seed=81)
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    f[0].load(W.embed(u0, 4))
+    f[1].load(W.embed(um1, 4))
+    f[2].load(W.embed(beta, 4))
+    out = plan.field()
+    out.load(np.full(plan.layout.extents, 7.0))
+    lo, hi = [3, 0, 10], [20, 30, 44]
+    plan.apply(out, f, lo, hi)
+    torch.cuda.synchronize()
+    got = out.interior(4)
+    ra, _, _ = oracle_wave(u0, um1, beta, 4, 4, 1)
+    box = tuple(slice(a, b) for a, b in zip(lo, hi))
+    assert rel_err(got[box], ra[box]) <= TOL_F32
+    mask = np.ones(shape, bool)
+    mask[box] = False
+    assert np.all(got[mask] == 7.0)
+
+
+def test_empty_interior_is_a_no_op(device):
+    plan = S.Plan(S.WAVE2, (0, 10, 10), 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    plan.run(f, 5)
+    plan2 = S.Plan(S.HEAT, (0,), 1, S.heat_weights(2, 0.1))
+    g = [plan2.field() for _ in range(2)]
+    plan2.run(g, 3)
