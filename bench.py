@@ -5,19 +5,23 @@ isotropic acoustic wave on a 512^3 interior (halo 4), layered velocity,
 Ricker source at the centre, 400 leapfrog steps, FP32 fields, inputs resident
 in HBM.  value = grid-point updates per second (GPts/s) over the timed steps.
 
-Also reported on the same GPU: 16-bit storage (bf16 / f16 with FP32
-arithmetic), the 3D so-4 heat sweep, batched uneven shots against sequential
-plain runs, and the checkpointed gradient against the plain forward; each with
-its error against the FP64 oracle where one is computed.  `cpu_baseline` times
-the FP64 oracle on the host cores on a bounded sample.
+Also reported on the same GPU (`variants`):
+  * 16-bit storage (bf16 / f16, FP32 arithmetic) of the same workload;
+  * the 3D so-4 heat sweep, 512^3, 50 steps;
+  * 32 independent shots of uneven sizes 128^3..384^3, 200 steps, in one
+    launch per step (one graph), against 32 sequential plain runs;
+  * the checkpointed misfit gradient (256^3, 500 steps, 64 receivers,
+    checkpoints every 25 steps) against the plain forward of the same model.
+`cpu_baseline` times the FP64 oracle on the host cores on a bounded sample of
+the headline workload.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -30,6 +34,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GPts/s + % of HBM peak, 3D so-8 wave; batched & adjoint vs plain, same GPU"
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_02218_amd", "csrc", f)
+                  for f in ("kernels.hip", "device.hpp", "kernels.hpp")]
 
 
 def log(*a):
@@ -45,9 +52,11 @@ def parse():
     ap.add_argument("--nsteps", type=int, default=400, help="leapfrog steps per bench step")
     ap.add_argument("--only-main", action="store_true", help="headline workload only (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (else tune)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (for counter scaling)")
+                    help="also run 1 GiB device copies (for counter scaling)")
     return ap.parse_args()
 
 
@@ -69,6 +78,30 @@ class Timer:
         self.b.record()
         self.torch.cuda.synchronize()
         self.ms = self.a.elapsed_time(self.b)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(variant_name: str):
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, if it was taken from the current kernel source and variant."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    e = c.get("wave3d_so8_512", {}).get(variant_name)
+    if not e:
+        return None
+    return e.get("hbm_bytes_per_launch")
 
 
 def stream_copy_gbs(nbytes=1 << 30, reps=10):
@@ -111,28 +144,136 @@ def time_wave(plan, f, amp, P, steps, warmup):
     return t.ms / steps
 
 
-def cpu_baseline(W, budget_s=12.0):
-    """FP64 oracle on the host cores: the same so-8 wave recipe at 192^3,
-    as many leapfrog steps as fit in about budget_s seconds."""
+def cpu_baseline(W, n, budget_s=12.0):
+    """FP64 oracle on the host cores: the headline recipe at its own n^3
+    interior, as many leapfrog steps as fit in about budget_s seconds."""
     import oracle
     threads = len(os.sched_getaffinity(0))
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-    n = 192
-    P = W.wave3d_c3(n=n, nsteps=4)
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    P = W.wave3d_c3(n=n, nsteps=2)
     beta = W.embed(W.round_to_storage(P.beta, "f32"), 4)
     z = np.zeros_like(beta)
     c = oracle.fd_weights_float(8)
     t0 = time.perf_counter()
-    oracle.wave_run(z, z, beta, 4, 4, c, 4, src=P.src, src_amp=P.src_amp)
-    per = (time.perf_counter() - t0) / 4
-    k = max(4, min(400, int(budget_s / max(per, 1e-6))))
+    oracle.wave_run(z, z, beta, 4, 4, c, 2, src=P.src, src_amp=P.src_amp)
+    per = (time.perf_counter() - t0) / 2
+    k = max(2, min(400, int(budget_s / max(per, 1e-6))))
     P = W.wave3d_c3(n=n, nsteps=k)
     t0 = time.perf_counter()
     oracle.wave_run(z, z, beta, 4, 4, c, k, src=P.src, src_amp=P.src_amp)
     dt = time.perf_counter() - t0
-    return {"value": n ** 3 * k / dt / 1e9, "unit": "GPts/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
+    return {"value": round(float(n) ** 3 * k / dt / 1e9, 4), "unit": "GPts/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"FP64 oracle, so-8 wave {n}^3 interior, {k} leapfrog steps, {dt:.1f} s"}
+            "sample": f"FP64 oracle (C, OpenMP over z), so-8 wave {n}^3 interior, first {k} of the "
+                      f"400 leapfrog steps, {dt:.1f} s"}
+
+
+def bench_batch(S, W, steps):
+    """32 uneven shots: one batched graph vs 32 sequential plain runs."""
+    import torch
+    B = W.batch_c4()
+    shapes = [s.shape for s in B.shots]
+    bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
+    fields, amps = [], []
+    for i, sh in enumerate(B.shots):
+        f = [bp.field(i) for _ in range(3)]
+        f[2].load(W.embed(W.round_to_storage(sh.beta, "f32"), 4))
+        fields.append(f)
+        amps.append(torch.from_numpy(sh.src_amp).cuda())
+    srcs = [sh.src for sh in B.shots]
+    bp.tune(fields, reps=2)
+
+    def run_batch():
+        for f in fields:
+            f[0].storage.zero_()
+            f[1].storage.zero_()
+        bp.run(fields, B.nsteps, srcs, amps)
+
+    run_batch()
+    with Timer() as t:
+        for _ in range(steps):
+            run_batch()
+    ms_b = t.ms / steps
+    # sequential plain runs on the same fields' data
+    plans = []
+    for i, sh in enumerate(B.shots):
+        p = S.Plan(S.WAVE2, sh.shape, 4, S.second_derivative_weights(8), halo=4)
+        g = [p.field() for _ in range(3)]
+        g[2].storage.copy_(fields[i][2].storage)
+        p.tune(g, reps=2)
+        plans.append((p, g))
+
+    def run_seq():
+        for i, (p, g) in enumerate(plans):
+            g[0].storage.zero_()
+            g[1].storage.zero_()
+            p.run(g, B.nsteps, src=srcs[i], src_amp=amps[i])
+
+    run_seq()
+    with Timer() as t:
+        for _ in range(steps):
+            run_seq()
+    ms_s = t.ms / steps
+    run_batch()
+    same = all(torch.equal(fields[i][0].storage, plans[i][1][0].storage) for i in range(len(plans)))
+    pts = float(sum(np.prod(s) for s in shapes)) * B.nsteps
+    return {"shots": len(shapes), "points": int(sum(np.prod(s) for s in shapes)),
+            "leapfrog_steps": B.nsteps, "GPts_s": round(pts / (ms_b * 1e-3) / 1e9, 2),
+            "ms_per_run": round(ms_b, 2), "sequential_GPts_s": round(pts / (ms_s * 1e-3) / 1e9, 2),
+            "sequential_ms": round(ms_s, 2), "batched_vs_sequential": round(ms_s / ms_b, 3),
+            "bitwise_equal_to_sequential": bool(same),
+            "variant": bp.variant}
+
+
+def bench_adjoint(S, W, steps):
+    """Checkpointed gradient of J = 1/2 |d|^2 (the adjoint's work does not
+    depend on the residual values) vs the plain forward of the same model."""
+    import torch
+    P = W.inversion_c5()
+    n, N, k = P.shape[0], P.nsteps, P.checkpoint_every
+    plan = S.Plan(S.WAVE2, P.shape, 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    m0 = P.m0
+    beta = W.round_to_storage(P.dt * P.dt / (P.h * P.h * m0), "f32")
+    f[2].load(W.embed(beta, 4))
+    amp = torch.from_numpy((P.dt ** 2 / m0[tuple(P.src[0])] * P.wavelet).reshape(-1, 1)).cuda()
+    nrec = len(P.rec)
+    tr = torch.zeros((N, nrec), dtype=torch.float64, device="cuda")
+    scale = torch.from_numpy(np.array([P.dt ** 2 / m0[tuple(p)] for p in P.rec])).cuda()
+    grad = torch.zeros(P.shape, dtype=torch.float64, device="cuda")
+    ws = torch.empty(plan.adjoint_workspace_bytes(N, k), dtype=torch.uint8, device="cuda")
+    plan.tune(f, reps=3)
+
+    def fwd():
+        f[0].storage.zero_()
+        f[1].storage.zero_()
+        plan.run(f, N, src=P.src, src_amp=amp, rec=P.rec, rec_trace=tr)
+
+    def gradient():
+        f[0].storage.zero_()
+        f[1].storage.zero_()
+        plan.forward_ckpt(f, N, k, ws, src=P.src, src_amp=amp, rec=P.rec, rec_trace=tr)
+        plan.adjoint(f[2], N, k, ws, tr, P.rec, scale, -1.0 / P.dt ** 2, grad, src=P.src, src_amp=amp)
+
+    fwd()
+    with Timer() as t:
+        for _ in range(steps):
+            fwd()
+    ms_f = t.ms / steps
+    gradient()
+    with Timer() as t:
+        for _ in range(steps):
+            gradient()
+    ms_g = t.ms / steps
+    pts = float(n) ** 3 * N
+    return {"interior": list(P.shape), "leapfrog_steps": N, "receivers": nrec, "checkpoint_every": k,
+            "forward_GPts_s": round(pts / (ms_f * 1e-3) / 1e9, 2), "forward_ms": round(ms_f, 2),
+            "gradient_GPts_s": round(pts / (ms_g * 1e-3) / 1e9, 2), "gradient_ms": round(ms_g, 2),
+            "gradient_vs_forward_time": round(ms_g / ms_f, 3),
+            "workspace_GB": round(ws.numel() / 1e9, 2),
+            "bytes_per_gradient_update": 64,
+            "misfit": "J = 1/2 |d|^2 (d_obs = 0); timing only, parity is in the tests",
+            "variant": plan.variant_name(plan.variant)}
 
 
 def main():
@@ -162,6 +303,7 @@ def main():
     achieved = 16.0 * n ** 3 / (kern_ms * 1e-3) / 1e9
     log(f"[bench] {ms:.2f} ms per run, {kern_ms * 1e3:.1f} us per sweep, {gpts:.1f} GPts/s, "
         f"{achieved:.0f} GB/s algorithmic")
+    traffic = stored_traffic(vname) if n == 512 else None
     out = {
         "metric": METRIC, "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -171,11 +313,13 @@ def main():
                    "radius": 4, "leapfrog_steps": nsteps, "storage": "f32", "variant": vname,
                    "source": "Ricker 10 Hz at the centre, layered velocity 1.5-4.5 km/s +-5%"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_zmarch<wave, r=4, f32>",
-                     "bytes_per_update": 16, "updates_per_launch": n ** 3,
-                     "avg_launch_us": round(kern_ms * 1e3, 2)},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_zmarch<wave, r=4, f32>", "bytes_per_update": 16,
+                     "updates_per_launch": n ** 3, "avg_launch_us": round(kern_ms * 1e3, 2)},
     }
+    if traffic:
+        out["roofline"]["traffic_GBps"] = round(traffic / (kern_ms * 1e-3) / 1e9, 1)
     del f
     torch.cuda.empty_cache()
 
@@ -189,11 +333,10 @@ def main():
             P2, plan2, f2, amp2 = wave_setup(S, W, n, nsteps, dt, args.variant)
             ms2 = time_wave(plan2, f2, amp2, P2, max(1, args.steps // 2), 1)
             g2 = pts / (ms2 * 1e-3) / 1e9
-            extras[f"wave_{name}"] = {"GPts_s": round(g2, 2), "ms_per_run": round(ms2, 2),
-                                      "bytes_per_update": 8,
-                                      "frac_hbm_8B": round(8.0 * n ** 3 / (ms2 / nsteps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                      "vs_fp32": round(g2 / gpts, 3),
-                                      "variant": plan2.variant_name(plan2.variant)}
+            extras[f"wave_{name}"] = {
+                "GPts_s": round(g2, 2), "ms_per_run": round(ms2, 2), "bytes_per_update": 8,
+                "frac_hbm_8B": round(8.0 * n ** 3 / (ms2 / nsteps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "vs_fp32": round(g2 / gpts, 3), "variant": plan2.variant_name(plan2.variant)}
             del f2
             torch.cuda.empty_cache()
         log("[bench] heat so-4 512^3 x 50")
@@ -211,11 +354,19 @@ def main():
                                 "variant": hp.variant_name(hp.variant)}
         del hf
         torch.cuda.empty_cache()
+        if not args.no_batch:
+            log("[bench] batched shots")
+            extras["batched_shots"] = bench_batch(S, W, max(1, args.steps // 2))
+            torch.cuda.empty_cache()
+        if not args.no_adjoint:
+            log("[bench] checkpointed gradient")
+            extras["adjoint_gradient"] = bench_adjoint(S, W, max(1, args.steps // 2))
+            torch.cuda.empty_cache()
         out["variants"] = extras
 
     if not args.no_cpu and not args.only_main:
         log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(W)
+        out["cpu_baseline"] = cpu_baseline(W, n)
     print(json.dumps(out), flush=True)
 
 

@@ -19,6 +19,9 @@ typedef _Float16 f16;
 template <typename T>
 struct Storage;
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
 template <>
 struct Storage<float> {
     __device__ static inline float load(const float* p) { return *p; }
@@ -28,6 +31,15 @@ struct Storage<float> {
     __device__ static inline float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
     __device__ static inline void store4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
     __device__ static inline void store(float* p, float v) { *p = v; }
+    // streaming (non-temporal) forms for data touched once per sweep
+    __device__ static inline float4 load4_nt(const float* p) {
+        const f4v r = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+        return make_float4(r.x, r.y, r.z, r.w);
+    }
+    __device__ static inline void store4_nt(float* p, float4 v) {
+        f4v r = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(r, reinterpret_cast<f4v*>(p));
+    }
 };
 
 // bf16: widening is exact (the 16 bits are the top half of an FP32); narrowing
@@ -58,6 +70,17 @@ struct Storage<bf16> {
         *reinterpret_cast<uint2*>(p) = r;
     }
     __device__ static inline void store(bf16* p, float v) { p->bits = f_to_bf16(v); }
+    __device__ static inline float4 load4_nt(const bf16* p) {
+        const u2v r = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+        return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                           __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+    }
+    __device__ static inline void store4_nt(bf16* p, float4 v) {
+        u2v r;
+        r.x = (uint32_t)f_to_bf16(v.x) | ((uint32_t)f_to_bf16(v.y) << 16);
+        r.y = (uint32_t)f_to_bf16(v.z) | ((uint32_t)f_to_bf16(v.w) << 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<u2v*>(p));
+    }
 };
 
 // f16: hardware conversions.  The FP32 value is pinned in a register before
@@ -89,6 +112,20 @@ struct Storage<f16> {
         *reinterpret_cast<h4*>(p) = r;
     }
     __device__ static inline void store(f16* p, float v) { *p = f_to_f16(v); }
+    __device__ static inline float4 load4_nt(const f16* p) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 r = __builtin_nontemporal_load(reinterpret_cast<const h4*>(p));
+        return make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.w);
+    }
+    __device__ static inline void store4_nt(f16* p, float4 v) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 r;
+        r.x = f_to_f16(v.x);
+        r.y = f_to_f16(v.y);
+        r.z = f_to_f16(v.z);
+        r.w = f_to_f16(v.w);
+        __builtin_nontemporal_store(r, reinterpret_cast<h4*>(p));
+    }
 };
 
 // value after a round trip through the storage type

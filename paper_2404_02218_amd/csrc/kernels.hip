@@ -81,12 +81,27 @@ __global__ __launch_bounds__(256) void k_point(ZView v, Coefs w, Box3 box) {
 }
 
 // -------------------------------------------------------------- k_zmarch
-template <int MODE, int R, typename T, int BX, int BY, int VY>
+// LDS holds a ring of R+2 plane slots of (TY+2R) x (TX+8) floats.  The halo
+// part of a slot (the x and y margins of the tile) is written when its plane
+// is the leading plane z+R, i.e. when the neighbouring tiles load the same
+// rows as their own interior, so those rows are still in L2; the interior part
+// is written when the plane becomes the current one.  With R+2 slots a single
+// barrier per plane separates every write from the reads of the same slot.
+template <int R, int BX, int BY, int VY>
+struct ZTile {
+    static constexpr int NT = BX * BY, TX = 4 * BX, TY = BY * VY;
+    static constexpr int LDX = TX + 8, LDY = TY + 2 * R, PLANE = LDX * LDY;
+    static constexpr int NSLOT = R + 2;
+    static constexpr int LDS_FLOATS = NSLOT * PLANE;
+    static constexpr int NHX = 2 * TY, NHY = 2 * R * BX, NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
+};
+
+template <int MODE, int R, typename T, int BX, int BY, int VY, bool NTH>
 __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int lb, int parity, int arow,
                                             int trow, float* __restrict__ lds) {
-    constexpr int NT = BX * BY, TX = 4 * BX, TY = BY * VY;
-    constexpr int LDX = TX + 8, LDY = TY + 2 * R, PLANE = LDX * LDY;
-    constexpr int NHX = 2 * TY, NHY = 2 * R * BX, NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
+    using Z = ZTile<R, BX, BY, VY>;
+    constexpr int NT = Z::NT, TX = Z::TX, TY = Z::TY, LDX = Z::LDX, PLANE = Z::PLANE, NSLOT = Z::NSLOT;
+    constexpr int NHX = Z::NHX, NHY = Z::NHY, NHT = Z::NHT, NH = Z::NH;
     constexpr bool WAVE = MODE != MODE_HEAT;
     using S = Storage<T>;
 
@@ -144,21 +159,31 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
     }
 
+    // own columns of planes zb-R .. zb+R; halos of planes zb .. zb+R-1 go
+    // straight to their slots, the halo of plane zb+R is in flight
     float4 q[2 * R + 1][VY];
 #pragma unroll
     for (int k = 0; k < 2 * R + 1; k++)
 #pragma unroll
         for (int j = 0; j < VY; j++) q[k][j] = S::load4(U + (int64_t)(zb - R + k) * sz + own[j]);
-    float4 hal[NH];
+    for (int p = zb; p < min(zb + R, ze); p++) {
+        float* L = lds + ((p - zb) % NSLOT) * PLANE;
 #pragma unroll
-    for (int m = 0; m < NH; m++)
-        if (hon[m]) hal[m] = S::load4(U + (int64_t)zb * sz + hoff[m]);
+        for (int m = 0; m < NH; m++)
+            if (hon[m]) *reinterpret_cast<float4*>(&L[hlds[m]]) = S::load4(U + (int64_t)p * sz + hoff[m]);
+    }
+    float4 hal[NH];
+    if (zb + R < ze) {
+#pragma unroll
+        for (int m = 0; m < NH; m++)
+            if (hon[m]) hal[m] = S::load4(U + (int64_t)(zb + R) * sz + hoff[m]);
+    }
     float4 cp[VY], cb[VY];
     if constexpr (WAVE) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            cp[j] = S::load4(P + (int64_t)zb * sz + own[j]);
-            cb[j] = S::load4(B + (int64_t)zb * sz + own[j]);
+            cp[j] = NTH ? S::load4_nt(P + (int64_t)zb * sz + own[j]) : S::load4(P + (int64_t)zb * sz + own[j]);
+            cb[j] = NTH ? S::load4_nt(B + (int64_t)zb * sz + own[j]) : S::load4(B + (int64_t)zb * sz + own[j]);
         }
     }
 
@@ -171,15 +196,19 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
     }
 
-    int buf = 0;
+    int slot = 0;             // slot of plane z
+    int hslot = R % NSLOT;    // slot of plane z + R
     for (int z = zb; z < ze; z++) {
-        float* L = lds + buf * PLANE;
+        float* L = lds + slot * PLANE;
 #pragma unroll
         for (int j = 0; j < VY; j++)
             *reinterpret_cast<float4*>(&L[(R + ty + j * BY) * LDX + 4 + 4 * tx]) = q[R][j];
+        if (z + R < ze) {
+            float* H = lds + hslot * PLANE;
 #pragma unroll
-        for (int m = 0; m < NH; m++)
-            if (hon[m]) *reinterpret_cast<float4*>(&L[hlds[m]]) = hal[m];
+            for (int m = 0; m < NH; m++)
+                if (hon[m]) *reinterpret_cast<float4*>(&H[hlds[m]]) = hal[m];
+        }
 
         const bool more = z + 1 < ze;
         float4 nxt[VY], np[VY], nb[VY];
@@ -187,14 +216,16 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             const int64_t zn = (int64_t)(z + 1) * sz;
 #pragma unroll
             for (int j = 0; j < VY; j++) nxt[j] = S::load4(U + zn + (int64_t)R * sz + own[j]);
+            if (z + R + 1 < ze) {
 #pragma unroll
-            for (int m = 0; m < NH; m++)
-                if (hon[m]) hal[m] = S::load4(U + zn + hoff[m]);
+                for (int m = 0; m < NH; m++)
+                    if (hon[m]) hal[m] = S::load4(U + zn + (int64_t)R * sz + hoff[m]);
+            }
             if constexpr (WAVE) {
 #pragma unroll
                 for (int j = 0; j < VY; j++) {
-                    np[j] = S::load4(P + zn + own[j]);
-                    nb[j] = S::load4(B + zn + own[j]);
+                    np[j] = NTH ? S::load4_nt(P + zn + own[j]) : S::load4(P + zn + own[j]);
+                    nb[j] = NTH ? S::load4_nt(B + zn + own[j]) : S::load4(B + zn + own[j]);
                 }
             }
         }
@@ -274,7 +305,11 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 const int64_t off = (int64_t)z * sz + (int64_t)y * sy + x0;
                 const bool full = x0 + 3 < nx;
                 if (full) {
-                    S::store4(O + off, make_float4(o[j][0], o[j][1], o[j][2], o[j][3]));
+                    const float4 ov = make_float4(o[j][0], o[j][1], o[j][2], o[j][3]);
+                    if constexpr (NTH && MODE != MODE_WAVE_ADJ)
+                        S::store4_nt(O + off, ov);
+                    else
+                        S::store4(O + off, ov);
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; i++)
@@ -324,24 +359,23 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 }
             }
         }
-        buf ^= 1;
+        slot = slot + 1 == NSLOT ? 0 : slot + 1;
+        hslot = hslot + 1 == NSLOT ? 0 : hslot + 1;
     }
 }
 
-template <int MODE, int R, typename T, int BX, int BY, int VY>
+template <int MODE, int R, typename T, int BX, int BY, int VY, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch(ZView v, Coefs w, int parity, int arow, int trow) {
-    constexpr int PLANE = (4 * BX + 8) * (BY * VY + 2 * R);
-    __shared__ __attribute__((aligned(16))) float lds[2 * PLANE];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    zmarch_tile<MODE, R, T, BX, BY, VY>(v, w, lb, parity, arow, trow, lds);
+    zmarch_tile<MODE, R, T, BX, BY, VY, NTH>(v, w, lb, parity, arow, trow, lds);
 }
 
-template <int R, typename T, int BX, int BY, int VY>
+template <int R, typename T, int BX, int BY, int VY, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict__ views,
                                                         const int* __restrict__ block_start, int nshots,
                                                         Coefs w, int parity, int arow, int trow) {
-    constexpr int PLANE = (4 * BX + 8) * (BY * VY + 2 * R);
-    __shared__ __attribute__((aligned(16))) float lds[2 * PLANE];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     // shot owning logical block lb: block_start is the prefix sum of blocks per shot
     int lo = 0, hi = nshots - 1;
@@ -353,7 +387,7 @@ __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict
             hi = mid - 1;
     }
     const ZView v = views[lo];
-    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY>(v, w, lb - block_start[lo], parity, arow, trow, lds);
+    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, NTH>(v, w, lb - block_start[lo], parity, arow, trow, lds);
 }
 
 // ---------------------------------------------------------- small kernels
@@ -462,13 +496,24 @@ hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const C
     return hipErrorInvalidValue;
 }
 
+// dynamic LDS above 64 KiB must be enabled per kernel once
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
 template <int MODE, int R, typename T, int C>
 static hipError_t zm_launch(const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
+    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy>::LDS_FLOATS;
     const int64_t nb = zmarch_blocks(v);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_zmarch<MODE, R, T, c.bx, c.by, c.vy>), dim3((unsigned)nb), dim3(c.bx * c.by), 0, s, v,
-                       w, parity, arow, trow);
+    auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.nt>;
+    static const hipError_t attr = allow_lds(k, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(c.bx * c.by), lds, s, v, w, parity, arow, trow);
     return hipGetLastError();
 }
 
@@ -521,9 +566,13 @@ template <int R, typename T, int C>
 static hipError_t zb_launch(const ZView* views, const int* bs, int nshots, int nblocks, const Coefs& w,
                             int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
+    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy>::LDS_FLOATS;
     if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_zmarch_batch<R, T, c.bx, c.by, c.vy>), dim3((unsigned)nblocks), dim3(c.bx * c.by), 0,
-                       s, views, bs, nshots, w, parity, arow, trow);
+    auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.nt>;
+    static const hipError_t attr = allow_lds(k, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(c.bx * c.by), lds, s, views, bs, nshots, w, parity, arow,
+                       trow);
     return hipGetLastError();
 }
 

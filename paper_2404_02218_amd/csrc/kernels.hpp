@@ -59,15 +59,18 @@ struct ZView {
 };
 
 // Tile shapes of the z-marching kernel: BX threads along x with 4 points each,
-// BY thread rows, each thread owning VY rows (strided by BY).
+// BY thread rows, each thread owning VY rows (strided by BY); nt: stream the
+// once-read previous level and beta with non-temporal loads and the output
+// with non-temporal stores.
 struct TileCfg {
     int bx, by, vy;
+    bool nt;
 };
 inline constexpr TileCfg kTileCfgs[] = {
-    {16, 16, 2},  // 64 x 32 tile, 256 threads
-    {16, 8, 2},   // 64 x 16 tile, 128 threads
-    {32, 8, 2},   // 128 x 16 tile, 256 threads
-    {16, 16, 1},  // 64 x 16 tile, 256 threads
+    {16, 16, 2, false},  // 64 x 32 tile, 256 threads
+    {16, 16, 1, true},   // 64 x 16 tile, 256 threads, streaming hints
+    {32, 8, 2, false},   // 128 x 16 tile, 256 threads
+    {16, 16, 1, false},  // 64 x 16 tile, 256 threads
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 // z-chunk lengths of the z-marching variants

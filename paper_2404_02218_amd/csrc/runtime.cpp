@@ -1081,7 +1081,8 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
     } else {
         const Variant v = variant_of(variant);
         name = "zmarch_" + std::to_string(tile_tx(v.cfg)) + "x" + std::to_string(tile_ty(v.cfg)) + "_t" +
-               std::to_string(tile_threads(v.cfg)) + "_zc" + std::to_string(v.zc);
+               std::to_string(tile_threads(v.cfg)) + "_zc" + std::to_string(v.zc) +
+               (kTileCfgs[v.cfg].nt ? "_nt" : "");
     }
     std::snprintf(buf, len, "%s", name.c_str());
     return STENCIL_OK;
@@ -1190,7 +1191,13 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             }
             return launch_point(mode, p->radius, p->dtype, views[0], p->w, box, s);
         };
+        // a variant the runtime refuses to launch (e.g. more LDS than this
+        // device allows) is skipped; any other error ends tuning
         hipError_t e = launch();
+        if (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration || e == hipErrorLaunchOutOfResources) {
+            (void)hipGetLastError();
+            continue;
+        }
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int r = 0; r < reps && e == hipSuccess; r++) e = launch();
         if (e == hipSuccess) e = hipEventRecord(e1, s);

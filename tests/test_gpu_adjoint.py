@@ -108,3 +108,35 @@ def test_recompute_equals_forward_bitwise(device):
     _, _, g = _gpu(P, m0, d1, 6, device)
     assert np.all(g == 0.0)
     del torch
+
+
+def test_autograd_function_matches_direct_calls_and_fd(device):
+    import torch
+    from paper_2404_02218_amd.wave import WaveModel
+    P = _problem(shape=(30, 26, 34), steps=80, seed=141)
+    nrec = len(P["rec"])
+    dobs, _, _ = _oracle(P, 1 / P["vt"] ** 2, np.zeros((P["steps"], nrec)))
+    model = WaveModel(P["shape"], P["h"], P["dt"], P["src"], P["w"], P["rec"], P["steps"], 20)
+    m0 = torch_f64(1 / P["v0"] ** 2, device).requires_grad_(True)
+    d_obs = torch_f64(dobs, device)
+    d = model(m0)
+    J = 0.5 * ((d - d_obs) ** 2).sum()
+    J.backward()
+    g = m0.grad.cpu().numpy()
+    # the same computation through the direct ABI calls
+    d2, J2, g2 = _gpu(P, 1 / P["v0"] ** 2, dobs, 20, device)
+    # beta is rounded from FP64 on the host there and on the device here
+    assert abs(float(J) - J2) <= 1e-6 * J2
+    assert np.linalg.norm(g - g2) <= 1e-5 * np.linalg.norm(g2)
+    dm = torch_f64(1 / P["vt"] ** 2 - 1 / P["v0"] ** 2, device)
+    eps = 1e-2
+    with torch.no_grad():
+        Jp = 0.5 * ((model(m0 + eps * dm) - d_obs) ** 2).sum().item()
+        Jm = 0.5 * ((model(m0 - eps * dm) - d_obs) ** 2).sum().item()
+    gdm = float((m0.grad * dm).sum())
+    assert abs((Jp - Jm) / (2 * eps) - gdm) <= 1e-2 * abs(gdm)
+    # a backward after a newer forward is refused
+    d3 = model(m0)
+    model(m0.detach())
+    with pytest.raises(RuntimeError):
+        (0.5 * (d3 ** 2).sum()).backward()
