@@ -32,6 +32,19 @@ struct Storage<float> {
     __device__ static inline void store4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
     __device__ static inline void store(float* p, float v) { *p = v; }
     // streaming (non-temporal) forms for data touched once per sweep
+    __device__ static inline void load8(const float* p, float4& a, float4& b, bool nt) {
+        a = nt ? load4_nt(p) : load4(p);
+        b = nt ? load4_nt(p + 4) : load4(p + 4);
+    }
+    __device__ static inline void store8(float* p, float4 a, float4 b, bool nt) {
+        if (nt) {
+            store4_nt(p, a);
+            store4_nt(p + 4, b);
+        } else {
+            store4(p, a);
+            store4(p + 4, b);
+        }
+    }
     __device__ static inline float4 load4_nt(const float* p) {
         const f4v r = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
         return make_float4(r.x, r.y, r.z, r.w);
@@ -70,6 +83,27 @@ struct Storage<bf16> {
         *reinterpret_cast<uint2*>(p) = r;
     }
     __device__ static inline void store(bf16* p, float v) { p->bits = f_to_bf16(v); }
+    // eight consecutive elements (16 bytes) as two float4
+    __device__ static inline void load8(const bf16* p, float4& a, float4& b, bool nt) {
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const u4v r = nt ? __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p)) : *reinterpret_cast<const u4v*>(p);
+        a = make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                        __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+        b = make_float4(__uint_as_float(r.z << 16), __uint_as_float(r.z & 0xffff0000u),
+                        __uint_as_float(r.w << 16), __uint_as_float(r.w & 0xffff0000u));
+    }
+    __device__ static inline void store8(bf16* p, float4 a, float4 b, bool nt) {
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        u4v r;
+        r.x = (uint32_t)f_to_bf16(a.x) | ((uint32_t)f_to_bf16(a.y) << 16);
+        r.y = (uint32_t)f_to_bf16(a.z) | ((uint32_t)f_to_bf16(a.w) << 16);
+        r.z = (uint32_t)f_to_bf16(b.x) | ((uint32_t)f_to_bf16(b.y) << 16);
+        r.w = (uint32_t)f_to_bf16(b.z) | ((uint32_t)f_to_bf16(b.w) << 16);
+        if (nt)
+            __builtin_nontemporal_store(r, reinterpret_cast<u4v*>(p));
+        else
+            *reinterpret_cast<u4v*>(p) = r;
+    }
     __device__ static inline float4 load4_nt(const bf16* p) {
         const u2v r = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
         return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
@@ -112,6 +146,28 @@ struct Storage<f16> {
         *reinterpret_cast<h4*>(p) = r;
     }
     __device__ static inline void store(f16* p, float v) { *p = f_to_f16(v); }
+    __device__ static inline void load8(const f16* p, float4& a, float4& b, bool nt) {
+        typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+        const h8 r = nt ? __builtin_nontemporal_load(reinterpret_cast<const h8*>(p)) : *reinterpret_cast<const h8*>(p);
+        a = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
+        b = make_float4((float)r[4], (float)r[5], (float)r[6], (float)r[7]);
+    }
+    __device__ static inline void store8(f16* p, float4 a, float4 b, bool nt) {
+        typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+        h8 r;
+        r[0] = f_to_f16(a.x);
+        r[1] = f_to_f16(a.y);
+        r[2] = f_to_f16(a.z);
+        r[3] = f_to_f16(a.w);
+        r[4] = f_to_f16(b.x);
+        r[5] = f_to_f16(b.y);
+        r[6] = f_to_f16(b.z);
+        r[7] = f_to_f16(b.w);
+        if (nt)
+            __builtin_nontemporal_store(r, reinterpret_cast<h8*>(p));
+        else
+            *reinterpret_cast<h8*>(p) = r;
+    }
     __device__ static inline float4 load4_nt(const f16* p) {
         typedef _Float16 h4 __attribute__((ext_vector_type(4)));
         const h4 r = __builtin_nontemporal_load(reinterpret_cast<const h4*>(p));
@@ -127,6 +183,26 @@ struct Storage<f16> {
         __builtin_nontemporal_store(r, reinterpret_cast<h4*>(p));
     }
 };
+
+// VX consecutive elements (VX = 4 or 8) at an aligned address, as floats
+template <typename T, int VX>
+__device__ static inline void load_vec(const T* p, float4 (&v)[VX / 4], bool nt) {
+    if constexpr (VX == 4)
+        v[0] = nt ? Storage<T>::load4_nt(p) : Storage<T>::load4(p);
+    else
+        Storage<T>::load8(p, v[0], v[1], nt);
+}
+template <typename T, int VX>
+__device__ static inline void store_vec(T* p, const float4 (&v)[VX / 4], bool nt) {
+    if constexpr (VX == 4) {
+        if (nt)
+            Storage<T>::store4_nt(p, v[0]);
+        else
+            Storage<T>::store4(p, v[0]);
+    } else {
+        Storage<T>::store8(p, v[0], v[1], nt);
+    }
+}
 
 // value after a round trip through the storage type
 template <typename T>

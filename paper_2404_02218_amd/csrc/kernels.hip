@@ -18,6 +18,8 @@
 //  small kernels: source injection / receiver sampling for k_point runs, box
 //            copies (halo pack, unpack, periodic self-exchange), zero fill,
 //            beta from squared slowness, FP64 gradient flush.
+#include <climits>
+
 #include "kernels.hpp"
 
 namespace stn {
@@ -87,21 +89,26 @@ __global__ __launch_bounds__(256) void k_point(ZView v, Coefs w, Box3 box) {
 // rows as their own interior, so those rows are still in L2; the interior part
 // is written when the plane becomes the current one.  With R+2 slots a single
 // barrier per plane separates every write from the reads of the same slot.
-template <int R, int BX, int BY, int VY>
+template <int R, int BX, int BY, int VY, int VX>
 struct ZTile {
-    static constexpr int NT = BX * BY, TX = 4 * BX, TY = BY * VY;
+    static constexpr int NT = BX * BY, TX = VX * BX, TY = BY * VY;
     static constexpr int LDX = TX + 8, LDY = TY + 2 * R, PLANE = LDX * LDY;
     static constexpr int NSLOT = R + 2;
     static constexpr int LDS_FLOATS = NSLOT * PLANE;
-    static constexpr int NHX = 2 * TY, NHY = 2 * R * BX, NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
+    // halo items are 4-element groups: one per side of each tile row, and
+    // TX/4 per halo row above and below the tile
+    static constexpr int NHX = 2 * TY, NHY = 2 * R * (TX / 4), NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
 };
 
-template <int MODE, int R, typename T, int BX, int BY, int VY, bool NTH>
+// Each thread owns VX consecutive x points (VX = 4 or 8) in VY rows strided
+// by BY; a row's VX values travel as VX/4 float4.
+template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int lb, int parity, int arow,
                                             int trow, float* __restrict__ lds) {
-    using Z = ZTile<R, BX, BY, VY>;
+    using Z = ZTile<R, BX, BY, VY, VX>;
     constexpr int NT = Z::NT, TX = Z::TX, TY = Z::TY, LDX = Z::LDX, PLANE = Z::PLANE, NSLOT = Z::NSLOT;
     constexpr int NHX = Z::NHX, NHY = Z::NHY, NHT = Z::NHT, NH = Z::NH;
+    constexpr int NV = VX / 4;
     constexpr bool WAVE = MODE != MODE_HEAT;
     using S = Storage<T>;
 
@@ -128,14 +135,15 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 
     // every load stays inside the field: x groups are clamped to the row,
     // y rows to the last halo row; clamped values only feed masked outputs
-    const int xmaxg = (int)(v.g.rowlen - v.g.xlead) - 4;
+    const int xmax4 = (int)(v.g.rowlen - v.g.xlead) - 4;
+    const int xmaxv = (int)(v.g.rowlen - v.g.xlead) - VX;
     const int ymax = ny + R - 1;
 
     int64_t own[VY];
 #pragma unroll
     for (int j = 0; j < VY; j++) {
         const int y = min(Y0 + ty + j * BY, ymax);
-        own[j] = (int64_t)y * sy + min(X0 + 4 * tx, xmaxg);
+        own[j] = (int64_t)y * sy + min(X0 + VX * tx, xmaxv);
     }
     int64_t hoff[NH];
     int hlds[NH];
@@ -147,25 +155,25 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         if (h < NHX) {
             const int r = h >> 1, side = h & 1;
             const int y = min(Y0 + r, ymax);
-            const int x = side ? min(X0 + TX, xmaxg) : X0 - 4;
+            const int x = side ? min(X0 + TX, xmax4) : X0 - 4;
             hoff[m] = (int64_t)y * sy + x;
             hlds[m] = (R + r) * LDX + (side ? 4 + TX : 0);
         } else {
             const int h2 = min(h - NHX, NHY - 1);
-            const int i = h2 / BX, g = h2 % BX;
+            const int i = h2 / (TX / 4), g = h2 % (TX / 4);
             const int y = i < R ? Y0 - R + i : min(Y0 + TY + (i - R), ymax);
-            hoff[m] = (int64_t)y * sy + min(X0 + 4 * g, xmaxg);
+            hoff[m] = (int64_t)y * sy + min(X0 + 4 * g, xmax4);
             hlds[m] = (i < R ? i : TY + i) * LDX + 4 + 4 * g;
         }
     }
 
     // own columns of planes zb-R .. zb+R; halos of planes zb .. zb+R-1 go
     // straight to their slots, the halo of plane zb+R is in flight
-    float4 q[2 * R + 1][VY];
+    float4 q[2 * R + 1][VY][NV];
 #pragma unroll
     for (int k = 0; k < 2 * R + 1; k++)
 #pragma unroll
-        for (int j = 0; j < VY; j++) q[k][j] = S::load4(U + (int64_t)(zb - R + k) * sz + own[j]);
+        for (int j = 0; j < VY; j++) load_vec<T, VX>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j], false);
     for (int p = zb; p < min(zb + R, ze); p++) {
         float* L = lds + ((p - zb) % NSLOT) * PLANE;
 #pragma unroll
@@ -178,21 +186,28 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         for (int m = 0; m < NH; m++)
             if (hon[m]) hal[m] = S::load4(U + (int64_t)(zb + R) * sz + hoff[m]);
     }
-    float4 cp[VY], cb[VY];
+    float4 cp[VY][NV], cb[VY][NV];
     if constexpr (WAVE) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            cp[j] = NTH ? S::load4_nt(P + (int64_t)zb * sz + own[j]) : S::load4(P + (int64_t)zb * sz + own[j]);
-            cb[j] = NTH ? S::load4_nt(B + (int64_t)zb * sz + own[j]) : S::load4(B + (int64_t)zb * sz + own[j]);
+            load_vec<T, VX>(P + (int64_t)zb * sz + own[j], cp[j], NTH);
+            load_vec<T, VX>(B + (int64_t)zb * sz + own[j], cb[j], NTH);
         }
     }
 
-    int sb = 0, se = 0;
+    // This tile's sources, sorted by z on the host: `snext` indexes the next
+    // one at or after the chunk start and `szn` holds its z in a register, so
+    // planes without a source cost one compare and no memory access (a load
+    // per plane would put its latency on this workgroup's critical path,
+    // and the slowest workgroup sets the duration of the whole launch).
+    int snext = 0, se = 0, szn = INT_MAX;
     if constexpr (WAVE) {
         if (v.src.n > 0) {
             const int tile = tile_y * v.ntx + tile_x;
-            sb = v.src.tile_begin[tile];
+            snext = v.src.tile_begin[tile];
             se = v.src.tile_begin[tile + 1];
+            while (snext < se && v.src.zyx4[4 * snext] < zb) snext++;
+            szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
         }
     }
 
@@ -202,7 +217,9 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         float* L = lds + slot * PLANE;
 #pragma unroll
         for (int j = 0; j < VY; j++)
-            *reinterpret_cast<float4*>(&L[(R + ty + j * BY) * LDX + 4 + 4 * tx]) = q[R][j];
+#pragma unroll
+            for (int c = 0; c < NV; c++)
+                *reinterpret_cast<float4*>(&L[(R + ty + j * BY) * LDX + 4 + VX * tx + 4 * c]) = q[R][j][c];
         if (z + R < ze) {
             float* H = lds + hslot * PLANE;
 #pragma unroll
@@ -211,11 +228,11 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
 
         const bool more = z + 1 < ze;
-        float4 nxt[VY], np[VY], nb[VY];
+        float4 nxt[VY][NV], np[VY][NV], nb[VY][NV];
         if (more) {
             const int64_t zn = (int64_t)(z + 1) * sz;
 #pragma unroll
-            for (int j = 0; j < VY; j++) nxt[j] = S::load4(U + zn + (int64_t)R * sz + own[j]);
+            for (int j = 0; j < VY; j++) load_vec<T, VX>(U + zn + (int64_t)R * sz + own[j], nxt[j], false);
             if (z + R + 1 < ze) {
 #pragma unroll
                 for (int m = 0; m < NH; m++)
@@ -224,44 +241,59 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             if constexpr (WAVE) {
 #pragma unroll
                 for (int j = 0; j < VY; j++) {
-                    np[j] = NTH ? S::load4_nt(P + zn + own[j]) : S::load4(P + zn + own[j]);
-                    nb[j] = NTH ? S::load4_nt(B + zn + own[j]) : S::load4(B + zn + own[j]);
+                    load_vec<T, VX>(P + zn + own[j], np[j], NTH);
+                    load_vec<T, VX>(B + zn + own[j], nb[j], NTH);
                 }
             }
         }
         __syncthreads();
 
-        float o[VY][4];
-        float dv[VY][4];
+        float o[VY][VX];
+        float dv[VY][VX];
 #pragma unroll
         for (int j = 0; j < VY; j++) {
             const int row = R + ty + j * BY;
-            const float* Lr = L + row * LDX + 4 * tx;
-            const float4 xl = *reinterpret_cast<const float4*>(Lr);
-            const float4 xr = *reinterpret_cast<const float4*>(Lr + 8);
-            float4 ym[R], yp[R];
+            const float* Lr = L + row * LDX + VX * tx;
+            // x taps: 4 left of the thread's points, its own VX, 4 right
+            float xv[VX + 8];
+            {
+                const float4 xl = *reinterpret_cast<const float4*>(Lr);
+                const float4 xr = *reinterpret_cast<const float4*>(Lr + 4 + VX);
+                xv[0] = xl.x;
+                xv[1] = xl.y;
+                xv[2] = xl.z;
+                xv[3] = xl.w;
 #pragma unroll
-            for (int k = 1; k <= R; k++) {
-                ym[k - 1] = *reinterpret_cast<const float4*>(L + (row - k) * LDX + 4 + 4 * tx);
-                yp[k - 1] = *reinterpret_cast<const float4*>(L + (row + k) * LDX + 4 + 4 * tx);
+                for (int i = 0; i < VX; i++) xv[4 + i] = comp(q[R][j][i / 4], i % 4);
+                xv[VX + 4] = xr.x;
+                xv[VX + 5] = xr.y;
+                xv[VX + 6] = xr.z;
+                xv[VX + 7] = xr.w;
             }
-            const float xv[12] = {xl.x, xl.y, xl.z, xl.w, q[R][j].x, q[R][j].y,
-                                  q[R][j].z, q[R][j].w, xr.x, xr.y, xr.z, xr.w};
+            float4 ym[R][NV], yp[R][NV];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const float ctr = comp(q[R][j], i);
+            for (int k = 1; k <= R; k++)
+#pragma unroll
+                for (int c = 0; c < NV; c++) {
+                    ym[k - 1][c] = *reinterpret_cast<const float4*>(L + (row - k) * LDX + 4 + VX * tx + 4 * c);
+                    yp[k - 1][c] = *reinterpret_cast<const float4*>(L + (row + k) * LDX + 4 + VX * tx + 4 * c);
+                }
+#pragma unroll
+            for (int i = 0; i < VX; i++) {
+                const int c = i / 4, e = i % 4;
+                const float ctr = comp(q[R][j][c], e);
                 float m[R], p[R];
                 float acc = w.cd0 * ctr;
 #pragma unroll
                 for (int k = 1; k <= R; k++) {
-                    m[k - 1] = comp(q[R - k][j], i);
-                    p[k - 1] = comp(q[R + k][j], i);
+                    m[k - 1] = comp(q[R - k][j][c], e);
+                    p[k - 1] = comp(q[R + k][j][c], e);
                 }
                 acc = axis_sum<R>(acc, w, m, p);
 #pragma unroll
                 for (int k = 1; k <= R; k++) {
-                    m[k - 1] = comp(ym[k - 1], i);
-                    p[k - 1] = comp(yp[k - 1], i);
+                    m[k - 1] = comp(ym[k - 1][c], e);
+                    p[k - 1] = comp(yp[k - 1][c], e);
                 }
                 acc = axis_sum<R>(acc, w, m, p);
 #pragma unroll
@@ -271,8 +303,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 }
                 acc = axis_sum<R>(acc, w, m, p);
                 if constexpr (WAVE) {
-                    o[j][i] = time_update<MODE>(acc, ctr, comp(cp[j], i), comp(cb[j], i));
-                    if constexpr (MODE == MODE_WAVE_D) dv[j][i] = comp(cb[j], i) * acc;
+                    o[j][i] = time_update<MODE>(acc, ctr, comp(cp[j][c], e), comp(cb[j][c], e));
+                    if constexpr (MODE == MODE_WAVE_D) dv[j][i] = comp(cb[j][c], e) * acc;
                 } else {
                     o[j][i] = time_update<MODE>(acc, ctr, 0.f, 0.f);
                 }
@@ -280,17 +312,18 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
 
         if constexpr (WAVE) {
-            for (int s = sb; s < se; s++) {
-                const int* e = v.src.zyx4 + 4 * s;
-                if (e[0] != z) continue;
+            while (szn == z) {
+                const int* e = v.src.zyx4 + 4 * snext;
+                snext++;
+                szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
                 const int dy = e[1] - Y0, dx = e[2] - X0;
                 const int idx = e[3];
                 const double amt = v.src.amp[(int64_t)arow * v.src.n + idx] * (v.src.scale ? v.src.scale[idx] : 1.0);
 #pragma unroll
                 for (int j = 0; j < VY; j++)
 #pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        if (dy == ty + j * BY && dx == 4 * tx + i) {
+                    for (int i = 0; i < VX; i++)
+                        if (dy == ty + j * BY && dx == VX * tx + i) {
                             o[j][i] = inject<T>(o[j][i], amt);
                             if constexpr (MODE == MODE_WAVE_D) dv[j][i] = (float)((double)dv[j][i] + amt);
                         }
@@ -300,45 +333,44 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
         for (int j = 0; j < VY; j++) {
             const int y = Y0 + ty + j * BY;
-            const int x0 = X0 + 4 * tx;
+            const int x0 = X0 + VX * tx;
             if (y < ny && x0 < nx) {
                 const int64_t off = (int64_t)z * sz + (int64_t)y * sy + x0;
-                const bool full = x0 + 3 < nx;
+                const bool full = x0 + VX - 1 < nx;
                 if (full) {
-                    const float4 ov = make_float4(o[j][0], o[j][1], o[j][2], o[j][3]);
-                    if constexpr (NTH && MODE != MODE_WAVE_ADJ)
-                        S::store4_nt(O + off, ov);
-                    else
-                        S::store4(O + off, ov);
+                    float4 ov[NV];
+#pragma unroll
+                    for (int c = 0; c < NV; c++)
+                        ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
+                    store_vec<T, VX>(O + off, ov, NTH && MODE != MODE_WAVE_ADJ);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 4; i++)
+                    for (int i = 0; i < VX; i++)
                         if (x0 + i < nx) S::store(O + off + i, o[j][i]);
                 }
                 if constexpr (MODE == MODE_WAVE_D) {
                     float* D = v.dfield + v.g.origin + off;
-                    if (full) {
-                        *reinterpret_cast<float4*>(D) = make_float4(dv[j][0], dv[j][1], dv[j][2], dv[j][3]);
-                    } else {
 #pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            if (x0 + i < nx) D[i] = dv[j][i];
-                    }
+                    for (int i = 0; i < VX; i++)
+                        if (x0 + i < nx) D[i] = dv[j][i];
                 }
                 if constexpr (MODE == MODE_WAVE_ADJ) {
                     const float* D = v.dfield + v.g.origin + off;
                     float* G = v.gfield + v.g.origin + off;
                     if (full) {
-                        const float4 d = *reinterpret_cast<const float4*>(D);
-                        float4 g = *reinterpret_cast<const float4*>(G);
-                        g.x = fmaf(o[j][0], d.x, g.x);
-                        g.y = fmaf(o[j][1], d.y, g.y);
-                        g.z = fmaf(o[j][2], d.z, g.z);
-                        g.w = fmaf(o[j][3], d.w, g.w);
-                        *reinterpret_cast<float4*>(G) = g;
+#pragma unroll
+                        for (int c = 0; c < NV; c++) {
+                            const float4 d = *reinterpret_cast<const float4*>(D + 4 * c);
+                            float4 g = *reinterpret_cast<const float4*>(G + 4 * c);
+                            g.x = fmaf(o[j][4 * c], d.x, g.x);
+                            g.y = fmaf(o[j][4 * c + 1], d.y, g.y);
+                            g.z = fmaf(o[j][4 * c + 2], d.z, g.z);
+                            g.w = fmaf(o[j][4 * c + 3], d.w, g.w);
+                            *reinterpret_cast<float4*>(G + 4 * c) = g;
+                        }
                     } else {
 #pragma unroll
-                        for (int i = 0; i < 4; i++)
+                        for (int i = 0; i < VX; i++)
                             if (x0 + i < nx) G[i] = fmaf(o[j][i], D[i], G[i]);
                     }
                 }
@@ -349,29 +381,33 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
             for (int k = 0; k < 2 * R; k++)
 #pragma unroll
-                for (int j = 0; j < VY; j++) q[k][j] = q[k + 1][j];
+                for (int j = 0; j < VY; j++)
 #pragma unroll
-            for (int j = 0; j < VY; j++) {
-                q[2 * R][j] = nxt[j];
-                if constexpr (WAVE) {
-                    cp[j] = np[j];
-                    cb[j] = nb[j];
+                    for (int c = 0; c < NV; c++) q[k][j][c] = q[k + 1][j][c];
+#pragma unroll
+            for (int j = 0; j < VY; j++)
+#pragma unroll
+                for (int c = 0; c < NV; c++) {
+                    q[2 * R][j][c] = nxt[j][c];
+                    if constexpr (WAVE) {
+                        cp[j][c] = np[j][c];
+                        cb[j][c] = nb[j][c];
+                    }
                 }
-            }
         }
         slot = slot + 1 == NSLOT ? 0 : slot + 1;
         hslot = hslot + 1 == NSLOT ? 0 : hslot + 1;
     }
 }
 
-template <int MODE, int R, typename T, int BX, int BY, int VY, bool NTH>
+template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch(ZView v, Coefs w, int parity, int arow, int trow) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    zmarch_tile<MODE, R, T, BX, BY, VY, NTH>(v, w, lb, parity, arow, trow, lds);
+    zmarch_tile<MODE, R, T, BX, BY, VY, VX, NTH>(v, w, lb, parity, arow, trow, lds);
 }
 
-template <int R, typename T, int BX, int BY, int VY, bool NTH>
+template <int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict__ views,
                                                         const int* __restrict__ block_start, int nshots,
                                                         Coefs w, int parity, int arow, int trow) {
@@ -387,7 +423,7 @@ __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict
             hi = mid - 1;
     }
     const ZView v = views[lo];
-    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, NTH>(v, w, lb - block_start[lo], parity, arow, trow, lds);
+    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, lb - block_start[lo], parity, arow, trow, lds);
 }
 
 // ---------------------------------------------------------- small kernels
@@ -507,10 +543,10 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 template <int MODE, int R, typename T, int C>
 static hipError_t zm_launch(const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     const int64_t nb = zmarch_blocks(v);
     if (nb == 0) return hipSuccess;
-    auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.nt>;
+    auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(k, lds);
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(c.bx * c.by), lds, s, v, w, parity, arow, trow);
@@ -524,6 +560,8 @@ static hipError_t zm_cfg(int cfg, const ZView& v, const Coefs& w, int parity, in
         case 1: return zm_launch<MODE, R, T, 1>(v, w, parity, arow, trow, s);
         case 2: return zm_launch<MODE, R, T, 2>(v, w, parity, arow, trow, s);
         case 3: return zm_launch<MODE, R, T, 3>(v, w, parity, arow, trow, s);
+        case 4: return zm_launch<MODE, R, T, 4>(v, w, parity, arow, trow, s);
+        case 5: return zm_launch<MODE, R, T, 5>(v, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }
@@ -566,9 +604,9 @@ template <int R, typename T, int C>
 static hipError_t zb_launch(const ZView* views, const int* bs, int nshots, int nblocks, const Coefs& w,
                             int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     if (nblocks == 0) return hipSuccess;
-    auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.nt>;
+    auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(k, lds);
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(c.bx * c.by), lds, s, views, bs, nshots, w, parity, arow,
@@ -585,6 +623,8 @@ static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bs,
         case 1: return zb_launch<4, T, 1>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
         case 2: return zb_launch<4, T, 2>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
         case 3: return zb_launch<4, T, 3>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
+        case 4: return zb_launch<4, T, 4>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
+        case 5: return zb_launch<4, T, 5>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }

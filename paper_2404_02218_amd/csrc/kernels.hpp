@@ -58,26 +58,29 @@ struct ZView {
     RecList rec;
 };
 
-// Tile shapes of the z-marching kernel: BX threads along x with 4 points each,
-// BY thread rows, each thread owning VY rows (strided by BY); nt: stream the
-// once-read previous level and beta with non-temporal loads and the output
-// with non-temporal stores.
+// Tile shapes of the z-marching kernel: BX threads along x with VX points
+// each, BY thread rows, each thread owning VY rows (strided by BY); nt: stream
+// the once-read previous level and beta with non-temporal loads and the
+// output with non-temporal stores.  VX = 8 gives 16-byte accesses for 16-bit
+// storage.
 struct TileCfg {
-    int bx, by, vy;
+    int bx, by, vy, vx;
     bool nt;
 };
 inline constexpr TileCfg kTileCfgs[] = {
-    {16, 16, 2, false},  // 64 x 32 tile, 256 threads
-    {16, 16, 1, true},   // 64 x 16 tile, 256 threads, streaming hints
-    {32, 8, 2, false},   // 128 x 16 tile, 256 threads
-    {16, 16, 1, false},  // 64 x 16 tile, 256 threads
+    {16, 16, 2, 4, false},  // 64 x 32 tile, 256 threads
+    {16, 16, 1, 4, true},   // 64 x 16 tile, 256 threads, streaming hints
+    {32, 8, 2, 4, false},   // 128 x 16 tile, 256 threads
+    {16, 16, 1, 4, false},  // 64 x 16 tile, 256 threads
+    {8, 32, 1, 8, true},    // 64 x 32 tile, 256 threads, 8 points per thread, streaming hints
+    {16, 16, 1, 8, true},   // 128 x 16 tile, 256 threads, 8 points per thread, streaming hints
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 // z-chunk lengths of the z-marching variants
 inline constexpr int kZChunks[] = {256, 128, 64, 32};
 inline constexpr int kNumZChunks = sizeof(kZChunks) / sizeof(kZChunks[0]);
 
-inline int tile_tx(int cfg) { return 4 * kTileCfgs[cfg].bx; }
+inline int tile_tx(int cfg) { return kTileCfgs[cfg].vx * kTileCfgs[cfg].bx; }
 inline int tile_ty(int cfg) { return kTileCfgs[cfg].by * kTileCfgs[cfg].vy; }
 inline int tile_threads(int cfg) { return kTileCfgs[cfg].bx * kTileCfgs[cfg].by; }
 

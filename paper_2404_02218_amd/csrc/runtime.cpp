@@ -285,24 +285,25 @@ stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int 
         const int TX = tile_tx(cfg), TY = tile_ty(cfg);
         const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
         const int nty = std::max(1, (L.g.n[1] + TY - 1) / TY);
-        std::vector<std::pair<int, int>> order((size_t)n);
+        // sort by (xy tile, z): the kernel walks a tile's sources in z order
+        std::vector<std::tuple<int, int, int>> order((size_t)n);
         for (int64_t i = 0; i < n; i++) {
             int zyx[3];
             zyx_of(L, pos + 3 * i, zyx);
-            order[i] = {(zyx[1] / TY) * ntx + zyx[2] / TX, (int)i};
+            order[i] = std::make_tuple((zyx[1] / TY) * ntx + zyx[2] / TX, zyx[0], (int)i);
         }
         std::stable_sort(order.begin(), order.end());
         std::vector<int> zyx4((size_t)std::max<int64_t>(4 * n, 4));
         std::vector<int> tb((size_t)ntx * nty + 1, 0);
         for (int64_t k = 0; k < n; k++) {
             int zyx[3];
-            const int i = order[k].second;
+            const int i = std::get<2>(order[k]);
             zyx_of(L, pos + 3 * i, zyx);
             zyx4[4 * k + 0] = zyx[0];
             zyx4[4 * k + 1] = zyx[1];
             zyx4[4 * k + 2] = zyx[2];
             zyx4[4 * k + 3] = i;
-            tb[order[k].first + 1]++;
+            tb[std::get<0>(order[k]) + 1]++;
         }
         for (size_t t = 1; t < tb.size(); t++) tb[t] += tb[t - 1];
         ST_TRY(T.zyx4.upload(zyx4.data(), sizeof(int) * (size_t)(4 * n)));
