@@ -21,7 +21,8 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("STENCIL_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
-SOURCES = ["kernels.hip", "runtime.cpp"]
+SOURCES = ["zmarch_f32.hip", "zmarch_adj.hip", "zmarch_bf16.hip", "zmarch_f16.hip", "kernels.hip",
+           "runtime.cpp"]
 
 
 def _compile(src: str) -> str:
@@ -35,7 +36,8 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

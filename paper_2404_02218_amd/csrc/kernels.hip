@@ -15,27 +15,14 @@
 //            by the first workgroup.
 //  k_zmarch_batch  the same tile body over a flattened tile list of many
 //            independent shots (one launch per step for all shots).
+//  (k_zmarch and k_zmarch_batch are templates in zmarch.hpp, instantiated
+//  per storage type in zmarch_*.hip; this file holds the rest.)
 //  small kernels: source injection / receiver sampling for k_point runs, box
 //            copies (halo pack, unpack, periodic self-exchange), zero fill,
 //            beta from squared slowness, FP64 gradient flush.
-#include <climits>
-
 #include "kernels.hpp"
 
 namespace stn {
-
-__device__ static inline float comp(const float4& v, int i) {
-    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
-// Give XCD x the contiguous logical range [x*q + min(x,r), ...) so that
-// neighbouring tiles (which read each other's edge rows as halo) share an L2.
-__device__ static inline int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
 
 // --------------------------------------------------------------- k_point
 template <int MODE, int R, typename T, int ND>
@@ -80,350 +67,6 @@ __global__ __launch_bounds__(256) void k_point(ZView v, Coefs w, Box3 box) {
         beta = S::load((const T*)v.beta + off);
     }
     S::store((T*)v.out + off, time_update<MODE>(acc, ctr, prev, beta));
-}
-
-// -------------------------------------------------------------- k_zmarch
-// LDS holds a ring of R+2 plane slots of (TY+2R) x (TX+8) floats.  The halo
-// part of a slot (the x and y margins of the tile) is written when its plane
-// is the leading plane z+R, i.e. when the neighbouring tiles load the same
-// rows as their own interior, so those rows are still in L2; the interior part
-// is written when the plane becomes the current one.  With R+2 slots a single
-// barrier per plane separates every write from the reads of the same slot.
-template <int R, int BX, int BY, int VY, int VX>
-struct ZTile {
-    static constexpr int NT = BX * BY, TX = VX * BX, TY = BY * VY;
-    static constexpr int LDX = TX + 8, LDY = TY + 2 * R, PLANE = LDX * LDY;
-    static constexpr int NSLOT = R + 2;
-    static constexpr int LDS_FLOATS = NSLOT * PLANE;
-    // halo items are 4-element groups: one per side of each tile row, and
-    // TX/4 per halo row above and below the tile
-    static constexpr int NHX = 2 * TY, NHY = 2 * R * (TX / 4), NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
-};
-
-// Each thread owns VX consecutive x points (VX = 4 or 8) in VY rows strided
-// by BY; a row's VX values travel as VX/4 float4.
-template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
-__device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int lb, int parity, int arow,
-                                            int trow, float* __restrict__ lds) {
-    using Z = ZTile<R, BX, BY, VY, VX>;
-    constexpr int NT = Z::NT, TX = Z::TX, TY = Z::TY, LDX = Z::LDX, PLANE = Z::PLANE, NSLOT = Z::NSLOT;
-    constexpr int NHX = Z::NHX, NHY = Z::NHY, NHT = Z::NHT, NH = Z::NH;
-    constexpr int NV = VX / 4;
-    constexpr bool WAVE = MODE != MODE_HEAT;
-    using S = Storage<T>;
-
-    const int tid = threadIdx.x;
-    const int tx = tid % BX, ty = tid / BX;
-    const int ntxy = v.ntx * v.nty;
-    const int tile_x = lb % v.ntx, tile_y = (lb / v.ntx) % v.nty, zch = lb / ntxy;
-    const int X0 = tile_x * TX, Y0 = tile_y * TY;
-    const int zb = zch * v.zc;
-    const int ze = min(zb + v.zc, v.g.n[0]);
-    const int nx = v.g.n[2], ny = v.g.n[1];
-    const int64_t sz = v.g.s[0], sy = v.g.s[1];
-
-    const T* U = (const T*)(parity ? v.prev : v.u) + v.g.origin;
-    const T* P = (const T*)(parity ? v.u : v.prev) + v.g.origin;
-    T* O = (T*)(parity ? (void*)v.u : v.out) + v.g.origin;
-    const T* B = (const T*)v.beta + v.g.origin;
-
-    // receivers sample the input level u^t (read-only during this launch)
-    if (trow >= 0 && lb == 0) {
-        for (int r = tid; r < v.rec.n; r += NT)
-            v.rec.trace[(int64_t)trow * v.rec.n + r] = (double)S::load(U + v.rec.off[r]);
-    }
-
-    // every load stays inside the field: x groups are clamped to the row,
-    // y rows to the last halo row; clamped values only feed masked outputs
-    const int xmax4 = (int)(v.g.rowlen - v.g.xlead) - 4;
-    const int xmaxv = (int)(v.g.rowlen - v.g.xlead) - VX;
-    const int ymax = ny + R - 1;
-
-    int64_t own[VY];
-#pragma unroll
-    for (int j = 0; j < VY; j++) {
-        const int y = min(Y0 + ty + j * BY, ymax);
-        own[j] = (int64_t)y * sy + min(X0 + VX * tx, xmaxv);
-    }
-    int64_t hoff[NH];
-    int hlds[NH];
-    bool hon[NH];
-#pragma unroll
-    for (int m = 0; m < NH; m++) {
-        const int h = tid + m * NT;
-        hon[m] = h < NHT;
-        if (h < NHX) {
-            const int r = h >> 1, side = h & 1;
-            const int y = min(Y0 + r, ymax);
-            const int x = side ? min(X0 + TX, xmax4) : X0 - 4;
-            hoff[m] = (int64_t)y * sy + x;
-            hlds[m] = (R + r) * LDX + (side ? 4 + TX : 0);
-        } else {
-            const int h2 = min(h - NHX, NHY - 1);
-            const int i = h2 / (TX / 4), g = h2 % (TX / 4);
-            const int y = i < R ? Y0 - R + i : min(Y0 + TY + (i - R), ymax);
-            hoff[m] = (int64_t)y * sy + min(X0 + 4 * g, xmax4);
-            hlds[m] = (i < R ? i : TY + i) * LDX + 4 + 4 * g;
-        }
-    }
-
-    // own columns of planes zb-R .. zb+R; halos of planes zb .. zb+R-1 go
-    // straight to their slots, the halo of plane zb+R is in flight
-    float4 q[2 * R + 1][VY][NV];
-#pragma unroll
-    for (int k = 0; k < 2 * R + 1; k++)
-#pragma unroll
-        for (int j = 0; j < VY; j++) load_vec<T, VX>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j], false);
-    for (int p = zb; p < min(zb + R, ze); p++) {
-        float* L = lds + ((p - zb) % NSLOT) * PLANE;
-#pragma unroll
-        for (int m = 0; m < NH; m++)
-            if (hon[m]) *reinterpret_cast<float4*>(&L[hlds[m]]) = S::load4(U + (int64_t)p * sz + hoff[m]);
-    }
-    float4 hal[NH];
-    if (zb + R < ze) {
-#pragma unroll
-        for (int m = 0; m < NH; m++)
-            if (hon[m]) hal[m] = S::load4(U + (int64_t)(zb + R) * sz + hoff[m]);
-    }
-    float4 cp[VY][NV], cb[VY][NV];
-    if constexpr (WAVE) {
-#pragma unroll
-        for (int j = 0; j < VY; j++) {
-            load_vec<T, VX>(P + (int64_t)zb * sz + own[j], cp[j], NTH);
-            load_vec<T, VX>(B + (int64_t)zb * sz + own[j], cb[j], NTH);
-        }
-    }
-
-    // This tile's sources, sorted by z on the host: `snext` indexes the next
-    // one at or after the chunk start and `szn` holds its z in a register, so
-    // planes without a source cost one compare and no memory access (a load
-    // per plane would put its latency on this workgroup's critical path,
-    // and the slowest workgroup sets the duration of the whole launch).
-    int snext = 0, se = 0, szn = INT_MAX;
-    if constexpr (WAVE) {
-        if (v.src.n > 0) {
-            const int tile = tile_y * v.ntx + tile_x;
-            snext = v.src.tile_begin[tile];
-            se = v.src.tile_begin[tile + 1];
-            while (snext < se && v.src.zyx4[4 * snext] < zb) snext++;
-            szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
-        }
-    }
-
-    int slot = 0;             // slot of plane z
-    int hslot = R % NSLOT;    // slot of plane z + R
-    for (int z = zb; z < ze; z++) {
-        float* L = lds + slot * PLANE;
-#pragma unroll
-        for (int j = 0; j < VY; j++)
-#pragma unroll
-            for (int c = 0; c < NV; c++)
-                *reinterpret_cast<float4*>(&L[(R + ty + j * BY) * LDX + 4 + VX * tx + 4 * c]) = q[R][j][c];
-        if (z + R < ze) {
-            float* H = lds + hslot * PLANE;
-#pragma unroll
-            for (int m = 0; m < NH; m++)
-                if (hon[m]) *reinterpret_cast<float4*>(&H[hlds[m]]) = hal[m];
-        }
-
-        const bool more = z + 1 < ze;
-        float4 nxt[VY][NV], np[VY][NV], nb[VY][NV];
-        if (more) {
-            const int64_t zn = (int64_t)(z + 1) * sz;
-#pragma unroll
-            for (int j = 0; j < VY; j++) load_vec<T, VX>(U + zn + (int64_t)R * sz + own[j], nxt[j], false);
-            if (z + R + 1 < ze) {
-#pragma unroll
-                for (int m = 0; m < NH; m++)
-                    if (hon[m]) hal[m] = S::load4(U + zn + (int64_t)R * sz + hoff[m]);
-            }
-            if constexpr (WAVE) {
-#pragma unroll
-                for (int j = 0; j < VY; j++) {
-                    load_vec<T, VX>(P + zn + own[j], np[j], NTH);
-                    load_vec<T, VX>(B + zn + own[j], nb[j], NTH);
-                }
-            }
-        }
-        __syncthreads();
-
-        float o[VY][VX];
-        float dv[VY][VX];
-#pragma unroll
-        for (int j = 0; j < VY; j++) {
-            const int row = R + ty + j * BY;
-            const float* Lr = L + row * LDX + VX * tx;
-            // x taps: 4 left of the thread's points, its own VX, 4 right
-            float xv[VX + 8];
-            {
-                const float4 xl = *reinterpret_cast<const float4*>(Lr);
-                const float4 xr = *reinterpret_cast<const float4*>(Lr + 4 + VX);
-                xv[0] = xl.x;
-                xv[1] = xl.y;
-                xv[2] = xl.z;
-                xv[3] = xl.w;
-#pragma unroll
-                for (int i = 0; i < VX; i++) xv[4 + i] = comp(q[R][j][i / 4], i % 4);
-                xv[VX + 4] = xr.x;
-                xv[VX + 5] = xr.y;
-                xv[VX + 6] = xr.z;
-                xv[VX + 7] = xr.w;
-            }
-            float4 ym[R][NV], yp[R][NV];
-#pragma unroll
-            for (int k = 1; k <= R; k++)
-#pragma unroll
-                for (int c = 0; c < NV; c++) {
-                    ym[k - 1][c] = *reinterpret_cast<const float4*>(L + (row - k) * LDX + 4 + VX * tx + 4 * c);
-                    yp[k - 1][c] = *reinterpret_cast<const float4*>(L + (row + k) * LDX + 4 + VX * tx + 4 * c);
-                }
-#pragma unroll
-            for (int i = 0; i < VX; i++) {
-                const int c = i / 4, e = i % 4;
-                const float ctr = comp(q[R][j][c], e);
-                float m[R], p[R];
-                float acc = w.cd0 * ctr;
-#pragma unroll
-                for (int k = 1; k <= R; k++) {
-                    m[k - 1] = comp(q[R - k][j][c], e);
-                    p[k - 1] = comp(q[R + k][j][c], e);
-                }
-                acc = axis_sum<R>(acc, w, m, p);
-#pragma unroll
-                for (int k = 1; k <= R; k++) {
-                    m[k - 1] = comp(ym[k - 1][c], e);
-                    p[k - 1] = comp(yp[k - 1][c], e);
-                }
-                acc = axis_sum<R>(acc, w, m, p);
-#pragma unroll
-                for (int k = 1; k <= R; k++) {
-                    m[k - 1] = xv[4 + i - k];
-                    p[k - 1] = xv[4 + i + k];
-                }
-                acc = axis_sum<R>(acc, w, m, p);
-                if constexpr (WAVE) {
-                    o[j][i] = time_update<MODE>(acc, ctr, comp(cp[j][c], e), comp(cb[j][c], e));
-                    if constexpr (MODE == MODE_WAVE_D) dv[j][i] = comp(cb[j][c], e) * acc;
-                } else {
-                    o[j][i] = time_update<MODE>(acc, ctr, 0.f, 0.f);
-                }
-            }
-        }
-
-        if constexpr (WAVE) {
-            while (szn == z) {
-                const int* e = v.src.zyx4 + 4 * snext;
-                snext++;
-                szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
-                const int dy = e[1] - Y0, dx = e[2] - X0;
-                const int idx = e[3];
-                const double amt = v.src.amp[(int64_t)arow * v.src.n + idx] * (v.src.scale ? v.src.scale[idx] : 1.0);
-#pragma unroll
-                for (int j = 0; j < VY; j++)
-#pragma unroll
-                    for (int i = 0; i < VX; i++)
-                        if (dy == ty + j * BY && dx == VX * tx + i) {
-                            o[j][i] = inject<T>(o[j][i], amt);
-                            if constexpr (MODE == MODE_WAVE_D) dv[j][i] = (float)((double)dv[j][i] + amt);
-                        }
-            }
-        }
-
-#pragma unroll
-        for (int j = 0; j < VY; j++) {
-            const int y = Y0 + ty + j * BY;
-            const int x0 = X0 + VX * tx;
-            if (y < ny && x0 < nx) {
-                const int64_t off = (int64_t)z * sz + (int64_t)y * sy + x0;
-                const bool full = x0 + VX - 1 < nx;
-                if (full) {
-                    float4 ov[NV];
-#pragma unroll
-                    for (int c = 0; c < NV; c++)
-                        ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
-                    store_vec<T, VX>(O + off, ov, NTH && MODE != MODE_WAVE_ADJ);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < VX; i++)
-                        if (x0 + i < nx) S::store(O + off + i, o[j][i]);
-                }
-                if constexpr (MODE == MODE_WAVE_D) {
-                    float* D = v.dfield + v.g.origin + off;
-#pragma unroll
-                    for (int i = 0; i < VX; i++)
-                        if (x0 + i < nx) D[i] = dv[j][i];
-                }
-                if constexpr (MODE == MODE_WAVE_ADJ) {
-                    const float* D = v.dfield + v.g.origin + off;
-                    float* G = v.gfield + v.g.origin + off;
-                    if (full) {
-#pragma unroll
-                        for (int c = 0; c < NV; c++) {
-                            const float4 d = *reinterpret_cast<const float4*>(D + 4 * c);
-                            float4 g = *reinterpret_cast<const float4*>(G + 4 * c);
-                            g.x = fmaf(o[j][4 * c], d.x, g.x);
-                            g.y = fmaf(o[j][4 * c + 1], d.y, g.y);
-                            g.z = fmaf(o[j][4 * c + 2], d.z, g.z);
-                            g.w = fmaf(o[j][4 * c + 3], d.w, g.w);
-                            *reinterpret_cast<float4*>(G + 4 * c) = g;
-                        }
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < VX; i++)
-                            if (x0 + i < nx) G[i] = fmaf(o[j][i], D[i], G[i]);
-                    }
-                }
-            }
-        }
-
-        if (more) {
-#pragma unroll
-            for (int k = 0; k < 2 * R; k++)
-#pragma unroll
-                for (int j = 0; j < VY; j++)
-#pragma unroll
-                    for (int c = 0; c < NV; c++) q[k][j][c] = q[k + 1][j][c];
-#pragma unroll
-            for (int j = 0; j < VY; j++)
-#pragma unroll
-                for (int c = 0; c < NV; c++) {
-                    q[2 * R][j][c] = nxt[j][c];
-                    if constexpr (WAVE) {
-                        cp[j][c] = np[j][c];
-                        cb[j][c] = nb[j][c];
-                    }
-                }
-        }
-        slot = slot + 1 == NSLOT ? 0 : slot + 1;
-        hslot = hslot + 1 == NSLOT ? 0 : hslot + 1;
-    }
-}
-
-template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
-__global__ __launch_bounds__(BX* BY) void k_zmarch(ZView v, Coefs w, int parity, int arow, int trow) {
-    extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    zmarch_tile<MODE, R, T, BX, BY, VY, VX, NTH>(v, w, lb, parity, arow, trow, lds);
-}
-
-template <int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
-__global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict__ views,
-                                                        const int* __restrict__ block_start, int nshots,
-                                                        Coefs w, int parity, int arow, int trow) {
-    extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    // shot owning logical block lb: block_start is the prefix sum of blocks per shot
-    int lo = 0, hi = nshots - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (block_start[mid] <= lb)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const ZView v = views[lo];
-    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, lb - block_start[lo], parity, arow, trow, lds);
 }
 
 // ---------------------------------------------------------- small kernels
@@ -532,99 +175,17 @@ hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const C
     return hipErrorInvalidValue;
 }
 
-// dynamic LDS above 64 KiB must be enabled per kernel once
-template <typename K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-    if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
-}
-
-template <int MODE, int R, typename T, int C>
-static hipError_t zm_launch(const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
-    constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
-    const int64_t nb = zmarch_blocks(v);
-    if (nb == 0) return hipSuccess;
-    auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
-    static const hipError_t attr = allow_lds(k, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(c.bx * c.by), lds, s, v, w, parity, arow, trow);
-    return hipGetLastError();
-}
-
-template <int MODE, int R, typename T>
-static hipError_t zm_cfg(int cfg, const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
-    switch (cfg) {
-        case 0: return zm_launch<MODE, R, T, 0>(v, w, parity, arow, trow, s);
-        case 1: return zm_launch<MODE, R, T, 1>(v, w, parity, arow, trow, s);
-        case 2: return zm_launch<MODE, R, T, 2>(v, w, parity, arow, trow, s);
-        case 3: return zm_launch<MODE, R, T, 3>(v, w, parity, arow, trow, s);
-        case 4: return zm_launch<MODE, R, T, 4>(v, w, parity, arow, trow, s);
-        case 5: return zm_launch<MODE, R, T, 5>(v, w, parity, arow, trow, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <int MODE, typename T>
-static hipError_t zm_r(int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow, int trow,
-                       hipStream_t s) {
-    switch (radius) {
-        case 1: return zm_cfg<MODE, 1, T>(cfg, v, w, parity, arow, trow, s);
-        case 2: return zm_cfg<MODE, 2, T>(cfg, v, w, parity, arow, trow, s);
-        case 3: return zm_cfg<MODE, 3, T>(cfg, v, w, parity, arow, trow, s);
-        case 4: return zm_cfg<MODE, 4, T>(cfg, v, w, parity, arow, trow, s);
-    }
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& v, const Coefs& w, int parity,
                          int arow, int trow, hipStream_t s) {
     if (mode == MODE_WAVE_D || mode == MODE_WAVE_ADJ) {
         // the adjoint path is FP32 only
         if (dtype != DT_F32) return hipErrorInvalidValue;
-        if (mode == MODE_WAVE_D) return zm_r<MODE_WAVE_D, float>(radius, cfg, v, w, parity, arow, trow, s);
-        return zm_r<MODE_WAVE_ADJ, float>(radius, cfg, v, w, parity, arow, trow, s);
+        return zmarch_adj_f32(mode, radius, cfg, v, w, parity, arow, trow, s);
     }
     switch (dtype) {
-        case DT_F32:
-            return mode == MODE_HEAT ? zm_r<MODE_HEAT, float>(radius, cfg, v, w, parity, arow, trow, s)
-                                     : zm_r<MODE_WAVE, float>(radius, cfg, v, w, parity, arow, trow, s);
-        case DT_BF16:
-            return mode == MODE_HEAT ? zm_r<MODE_HEAT, bf16>(radius, cfg, v, w, parity, arow, trow, s)
-                                     : zm_r<MODE_WAVE, bf16>(radius, cfg, v, w, parity, arow, trow, s);
-        case DT_F16:
-            return mode == MODE_HEAT ? zm_r<MODE_HEAT, f16>(radius, cfg, v, w, parity, arow, trow, s)
-                                     : zm_r<MODE_WAVE, f16>(radius, cfg, v, w, parity, arow, trow, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <int R, typename T, int C>
-static hipError_t zb_launch(const ZView* views, const int* bs, int nshots, int nblocks, const Coefs& w,
-                            int parity, int arow, int trow, hipStream_t s) {
-    constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
-    if (nblocks == 0) return hipSuccess;
-    auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
-    static const hipError_t attr = allow_lds(k, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(c.bx * c.by), lds, s, views, bs, nshots, w, parity, arow,
-                       trow);
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                         const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
-    if (radius != 4) return hipErrorInvalidValue;
-    switch (cfg) {
-        case 0: return zb_launch<4, T, 0>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 1: return zb_launch<4, T, 1>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 2: return zb_launch<4, T, 2>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 3: return zb_launch<4, T, 3>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 4: return zb_launch<4, T, 4>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 5: return zb_launch<4, T, 5>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
+        case DT_F32: return zmarch_fwd_f32(mode, radius, cfg, v, w, parity, arow, trow, s);
+        case DT_BF16: return zmarch_fwd_bf16(mode, radius, cfg, v, w, parity, arow, trow, s);
+        case DT_F16: return zmarch_fwd_f16(mode, radius, cfg, v, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }
@@ -633,9 +194,9 @@ hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_vi
                                int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
                                hipStream_t s) {
     switch (dtype) {
-        case DT_F32: return zb_cfg<float>(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
-        case DT_BF16: return zb_cfg<bf16>(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
-        case DT_F16: return zb_cfg<f16>(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
+        case DT_F32: return zmarch_batch_f32(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
+        case DT_BF16: return zmarch_batch_bf16(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
+        case DT_F16: return zmarch_batch_f16(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }

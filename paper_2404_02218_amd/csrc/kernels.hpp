@@ -72,8 +72,6 @@ inline constexpr TileCfg kTileCfgs[] = {
     {16, 16, 1, 4, true},   // 64 x 16 tile, 256 threads, streaming hints
     {32, 8, 2, 4, false},   // 128 x 16 tile, 256 threads
     {16, 16, 1, 4, false},  // 64 x 16 tile, 256 threads
-    {8, 32, 1, 8, true},    // 64 x 32 tile, 256 threads, 8 points per thread, streaming hints
-    {16, 16, 1, 8, true},   // 128 x 16 tile, 256 threads, 8 points per thread, streaming hints
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 // z-chunk lengths of the z-marching variants
@@ -107,6 +105,21 @@ hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& 
 hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_start,
                                int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
                                hipStream_t s);
+// per-storage-type instantiations (zmarch_*.hip)
+hipError_t zmarch_fwd_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
+                          int trow, hipStream_t s);
+hipError_t zmarch_fwd_bf16(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
+                           int trow, hipStream_t s);
+hipError_t zmarch_fwd_f16(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
+                          int trow, hipStream_t s);
+hipError_t zmarch_adj_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
+                          int trow, hipStream_t s);
+hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
+                            const Coefs& w, int parity, int arow, int trow, hipStream_t s);
+hipError_t zmarch_batch_bf16(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
+                             const Coefs& w, int parity, int arow, int trow, hipStream_t s);
+hipError_t zmarch_batch_f16(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
+                            const Coefs& w, int parity, int arow, int trow, hipStream_t s);
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s);
 hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecList& rec, int trow,
                          hipStream_t s);

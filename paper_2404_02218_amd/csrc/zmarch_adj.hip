@@ -1,0 +1,13 @@
+// Adjoint-path z-marching sweeps (FP32): forward recompute writing second differences, adjoint with imaging.
+#include "zmarch.hpp"
+
+namespace stn {
+
+hipError_t zmarch_adj_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
+                         int trow, hipStream_t s) {
+    if (mode == MODE_WAVE_D) return zm_r<MODE_WAVE_D, float>(radius, cfg, v, w, parity, arow, trow, s);
+    if (mode == MODE_WAVE_ADJ) return zm_r<MODE_WAVE_ADJ, float>(radius, cfg, v, w, parity, arow, trow, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stn

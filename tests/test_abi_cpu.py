@@ -126,7 +126,7 @@ def test_product_weights_equal_oracle_derivation():
 def test_variants_are_listed():
     p = S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8))
     n = p.variant_count()
-    assert n == 25
+    assert n == 17
     names = [p.variant_name(v) for v in range(n)]
     assert names[0] == "point" and len(set(names)) == n
     p2 = S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2))
