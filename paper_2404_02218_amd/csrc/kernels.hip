@@ -190,6 +190,16 @@ hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_tb2(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p,
+                      hipStream_t s) {
+    switch (dtype) {
+        case DT_F32: return tb2_f32(v, w, arow, trow_u, trow_p, s);
+        case DT_BF16: return tb2_bf16(v, w, arow, trow_u, trow_p, s);
+        case DT_F16: return tb2_f16(v, w, arow, trow_u, trow_p, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_start,
                                int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
                                hipStream_t s) {

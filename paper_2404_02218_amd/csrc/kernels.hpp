@@ -58,6 +58,25 @@ struct ZView {
     RecList rec;
 };
 
+// One field set as the depth-2 temporally blocked wave sweep sees it: inputs
+// u^n, u^{n-1}, beta; outputs u^{n+1}, u^{n+2} in two buffers that alias none
+// of the inputs.  Tiles are 64 x 32; src_t lists each tile's own sources,
+// src_e the sources within R points of the tile in x and y (a source appears
+// under every tile whose extended region holds it), both sorted by z.
+struct TBView {
+    const void* u;
+    const void* prev;
+    const void* beta;
+    void* out1;
+    void* out2;
+    Grid3 g;
+    int ntx, nty, zc, nzc;
+    SrcList src_t;
+    SrcList src_e;
+    RecList rec;
+    uint32_t range;   // bytes of each field's allocation (< 2^31)
+};
+
 // Tile shapes of the z-marching kernel: BX threads along x with VX points
 // each, BY thread rows, each thread owning VY rows (strided by BY); nt: stream
 // the once-read previous level and beta with non-temporal loads and the
@@ -120,6 +139,17 @@ hipError_t zmarch_batch_bf16(int radius, int cfg, const ZView* views, const int*
                              const Coefs& w, int parity, int arow, int trow, hipStream_t s);
 hipError_t zmarch_batch_f16(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
                             const Coefs& w, int parity, int arow, int trow, hipStream_t s);
+// depth-2 temporal blocking (radius 4, wave): steps arow and arow + 1;
+// receivers record u^n as row trow_u and u^{n-1} as row trow_p (if >= 0)
+hipError_t launch_tb2(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p,
+                      hipStream_t s);
+hipError_t tb2_f32(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
+hipError_t tb2_bf16(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
+hipError_t tb2_f16(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
+// tile shape, threads and z-chunk lengths of the temporally blocked sweep
+inline constexpr int kTB2TileX = 64, kTB2TileY = 32, kTB2Threads = 768;
+inline constexpr int kTB2ZChunks[] = {256, 128, 64};
+inline constexpr int kNumTB2ZChunks = sizeof(kTB2ZChunks) / sizeof(kTB2ZChunks[0]);
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s);
 hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecList& rec, int trow,
                          hipStream_t s);

@@ -152,17 +152,27 @@ struct DevTable {
     }
 };
 
+// Variant numbers: 0 = point kernel; 1 .. kNumZVariants = z-marching
+// (tile shape, z-chunk); then the depth-2 temporally blocked sweep, one per
+// z-chunk, where the plan supports it.
 struct Variant {
     bool zmarch = false;
+    bool tb = false;   // depth-2 temporal blocking (tile 64 x 32 = tile shape 0)
     int cfg = 0;
     int zc = 0;
 };
 
-int variant_count_for(int ndim) { return ndim == 3 ? 1 + kNumTileCfgs * kNumZChunks : 1; }
+constexpr int kNumZVariants = kNumTileCfgs * kNumZChunks;
 
 Variant variant_of(int v) {
     Variant r;
     if (v <= 0) return r;
+    if (v > kNumZVariants) {
+        r.tb = true;
+        r.cfg = 0;
+        r.zc = kTB2ZChunks[std::min(v - kNumZVariants - 1, kNumTB2ZChunks - 1)];
+        return r;
+    }
     r.zmarch = true;
     r.cfg = (v - 1) % kNumTileCfgs;
     r.zc = kZChunks[(v - 1) / kNumTileCfgs];
@@ -205,6 +215,8 @@ struct stencil_plan_s {
     int variant = 0;
     bool variant_forced = false;
     PointTables src, rec, adjrec;
+    PointTables src_ext;   // sources listed under every tile within R of them (temporal blocking)
+    DevBuf tb_pair[2];     // the second field pair of the temporally blocked sweep (zero halos)
     DevTable periodic_dummy;
     // graph cache of stencil_run
     hipStream_t cap = nullptr;
@@ -229,6 +241,21 @@ stencil_status check_plan(stencil_plan p, bool want_batch) {
     if (p->batch != want_batch)
         return fail(STENCIL_E_STATE, want_batch ? "not a batch plan" : "batch plan passed to a single-field call");
     return STENCIL_OK;
+}
+
+// The depth-2 temporally blocked sweep covers the 3D radius-4 wave with the
+// zero halo.  Its loads start 8 elements left of a tile and address a field
+// with 32-bit byte offsets.
+bool tb_supported(const stencil_plan_s* p) {
+    if (p->batch || p->ndim != 3 || p->kind != STENCIL_WAVE2 || p->radius != 4 || p->bc != STENCIL_BC_DIRICHLET0)
+        return false;
+    return p->L.g.xlead >= 8 && p->L.bytes < (int64_t(1) << 31);
+}
+
+int variant_count_of(const stencil_plan_s* p) {
+    if (p->batch) return kNumZVariants + 1;
+    if (p->ndim != 3) return 1;
+    return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
 }
 
 stencil_status check_ptr(const void* p, const char* what) {
@@ -275,8 +302,9 @@ void zyx_of(const Layout& L, const int64_t* p3, int out[3]) {
 }
 
 // Build the device tables of a point list for tile shape `cfg` (CSR over xy
-// tiles for the z-marching kernels; cfg < 0: offsets only).
-stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T) {
+// tiles for the z-marching kernels; cfg < 0: offsets only).  ext > 0 lists a
+// point under every tile whose box widened by `ext` in x and y holds it.
+stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T, int ext = 0) {
     T.n = (int)n;
     std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; i++) off[i] = interior_offset(L, pos + 3 * i);
@@ -286,16 +314,21 @@ stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int 
         const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
         const int nty = std::max(1, (L.g.n[1] + TY - 1) / TY);
         // sort by (xy tile, z): the kernel walks a tile's sources in z order
-        std::vector<std::tuple<int, int, int>> order((size_t)n);
+        std::vector<std::tuple<int, int, int>> order;
+        order.reserve((size_t)n);
         for (int64_t i = 0; i < n; i++) {
             int zyx[3];
             zyx_of(L, pos + 3 * i, zyx);
-            order[i] = std::make_tuple((zyx[1] / TY) * ntx + zyx[2] / TX, zyx[0], (int)i);
+            const int ty0 = std::max(0, (zyx[1] - ext) / TY), ty1 = std::min(nty - 1, (zyx[1] + ext) / TY);
+            const int tx0 = std::max(0, (zyx[2] - ext) / TX), tx1 = std::min(ntx - 1, (zyx[2] + ext) / TX);
+            for (int ty = ty0; ty <= ty1; ty++)
+                for (int tx = tx0; tx <= tx1; tx++) order.emplace_back(ty * ntx + tx, zyx[0], (int)i);
         }
         std::stable_sort(order.begin(), order.end());
-        std::vector<int> zyx4((size_t)std::max<int64_t>(4 * n, 4));
+        const int64_t m = (int64_t)order.size();
+        std::vector<int> zyx4((size_t)std::max<int64_t>(4 * m, 4));
         std::vector<int> tb((size_t)ntx * nty + 1, 0);
-        for (int64_t k = 0; k < n; k++) {
+        for (int64_t k = 0; k < m; k++) {
             int zyx[3];
             const int i = std::get<2>(order[k]);
             zyx_of(L, pos + 3 * i, zyx);
@@ -306,7 +339,7 @@ stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int 
             tb[std::get<0>(order[k]) + 1]++;
         }
         for (size_t t = 1; t < tb.size(); t++) tb[t] += tb[t - 1];
-        ST_TRY(T.zyx4.upload(zyx4.data(), sizeof(int) * (size_t)(4 * n)));
+        ST_TRY(T.zyx4.upload(zyx4.data(), sizeof(int) * (size_t)(4 * m)));
         ST_TRY(T.tiles.upload(tb.data(), sizeof(int) * tb.size()));
     }
     T.cfg = cfg;
@@ -411,11 +444,76 @@ void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out) {
     out.push_back(cl);
 }
 
+// Depth-2 temporally blocked run.  Each pass reads one field pair and
+// writes the other: the caller's (a, b) and the plan's tb_pair alternate, so
+// an even number of passes leaves u^{2K} in a and u^{2K-1} in b, as 2K plain
+// in-place steps would.  Remaining steps (nsteps mod 4 of them when the pass
+// count would be odd, else nsteps mod 2) run as plain z-marching sweeps on
+// the same 64 x 32 tiles.  Receivers: pass k records its two input levels
+// (rows 2k-1 and 2k-2); the level u^{2K-1} is recorded after the last pass.
+stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void* b, const void* beta,
+                              int64_t nsteps, const stencil_source* src, const stencil_receivers* rec,
+                              hipStream_t s) {
+    const Layout& L = p->L;
+    const SrcList st = src_list(p->src, src ? src->amp : nullptr, nullptr);
+    const SrcList se = src_list(p->src_ext, src ? src->amp : nullptr, nullptr);
+    const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    int64_t passes = nsteps / 2;
+    if (passes & 1) passes--;
+    void* pairs[2][2] = {{a, b}, {p->tb_pair[0].p, p->tb_pair[1].p}};
+    void* newest = a;
+    void* prev = b;
+    for (int64_t k = 0; k < passes; k++) {
+        void** dst = pairs[(k + 1) & 1];
+        TBView v{};
+        v.u = newest;
+        v.prev = prev;
+        v.beta = beta;
+        v.out1 = dst[1];
+        v.out2 = dst[0];
+        v.g = L.g;
+        v.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
+        v.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
+        v.zc = std::max(1, std::min(var.zc, L.g.n[0]));
+        v.nzc = (L.g.n[0] + v.zc - 1) / v.zc;
+        v.src_t = st;
+        v.src_e = se;
+        v.rec = rl;
+        v.range = (uint32_t)L.bytes;
+        const int tu = (rl.n > 0 && k >= 1) ? (int)(2 * k - 1) : -1;
+        const int tp = (rl.n > 0 && k >= 1) ? (int)(2 * k - 2) : -1;
+        HIP_TRY(launch_tb2(p->dtype, v, p->w, (int)(2 * k), tu, tp, s));
+        newest = dst[0];
+        prev = dst[1];
+    }
+    if (rl.n > 0 && passes > 0) HIP_TRY(launch_record(p->dtype, b, L.g, rl, (int)(2 * passes - 2), s));
+    Variant plain;
+    plain.zmarch = true;
+    plain.cfg = var.cfg;
+    plain.zc = var.zc;
+    for (int64_t t = 2 * passes; t < nsteps; t++) {
+        ZView v{};
+        v.u = a;
+        v.prev = b;
+        v.out = b;
+        v.beta = beta;
+        v.g = L.g;
+        set_tiling(v, L, plain);
+        v.src = st;
+        v.rec = rl;
+        const int trow = (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1;
+        HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, plain.cfg, v, p->w, (int)(t & 1), (int)t, trow, s));
+    }
+    if (rl.n > 0 && nsteps > 0) HIP_TRY(launch_record(p->dtype, (nsteps & 1) ? b : a, L.g, rl, (int)(nsteps - 1), s));
+    return STENCIL_OK;
+}
+
 // Enqueue nsteps sweeps of a single plan (no capture logic here).
 stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, int64_t nsteps,
                            const stencil_source* src, const stencil_receivers* rec, hipStream_t s) {
     const Layout& L = p->L;
     const Variant var = variant_of(p->variant);
+    if (var.tb) return enqueue_run_tb(p, var, a, b, beta, nsteps, src, rec, s);
     const bool wave = p->kind == STENCIL_WAVE2;
     const int mode = wave ? MODE_WAVE : MODE_HEAT;
     const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
@@ -598,9 +696,23 @@ static stencil_status run_args(stencil_plan p, void** fields, int64_t nsteps, co
 
 static stencil_status prepare_points(stencil_plan p, const stencil_source* src, const stencil_receivers* rec) {
     const Variant var = variant_of(p->variant);
-    const int cfg = var.zmarch ? var.cfg : -1;
+    const int cfg = (var.zmarch || var.tb) ? var.cfg : -1;
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, cfg, p->src));
+    if (var.tb) ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src_ext, 4));
     ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
+    return STENCIL_OK;
+}
+
+// the plan's second field pair, allocated with zero halos on first use
+// (before any capture: allocation and clearing synchronise the device)
+static stencil_status ensure_tb_pair(stencil_plan p) {
+    const size_t bytes = (size_t)p->L.bytes;
+    for (DevBuf& d : p->tb_pair) {
+        if (d.cap >= bytes && d.p) continue;
+        ST_TRY(d.ensure(bytes));
+        HIP_TRY(hipMemset(d.p, 0, d.cap));
+        HIP_TRY(hipDeviceSynchronize());
+    }
     return STENCIL_OK;
 }
 
@@ -613,6 +725,7 @@ stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const 
     void* a = fields[0];
     void* b = fields[1];
     const void* beta = p->kind == STENCIL_WAVE2 ? fields[2] : nullptr;
+    if (variant_of(p->variant).tb) ST_TRY(ensure_tb_pair(p));
     if (nsteps >= 2 && graphs_enabled()) {
         std::vector<int64_t> key = {(int64_t)(uintptr_t)a,
                                     (int64_t)(uintptr_t)b,
@@ -625,6 +738,10 @@ stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const 
                                     (int64_t)(uintptr_t)p->rec.off.buf.p,
                                     (int64_t)(uintptr_t)p->src.zyx4.buf.p,
                                     (int64_t)(uintptr_t)p->src.tiles.buf.p,
+                                    (int64_t)(uintptr_t)p->src_ext.zyx4.buf.p,
+                                    (int64_t)(uintptr_t)p->src_ext.tiles.buf.p,
+                                    (int64_t)(uintptr_t)p->tb_pair[0].p,
+                                    (int64_t)(uintptr_t)p->tb_pair[1].p,
                                     p->src.n,
                                     p->rec.n};
         if (!p->gexec || key != p->gkey) {
@@ -1067,7 +1184,7 @@ stencil_status stencil_wave_beta(stencil_plan p, const double* m, double dt, dou
 stencil_status stencil_variant_count(stencil_plan p, int* count) {
     if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
     if (!count) return fail(STENCIL_E_INVALID, "count is NULL");
-    *count = p->batch ? kNumTileCfgs * kNumZChunks + 1 : variant_count_for(p->ndim);
+    *count = variant_count_of(p);
     return STENCIL_OK;
 }
 
@@ -1079,6 +1196,9 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
     std::string name;
     if (variant == 0) {
         name = "point";
+    } else if (variant_of(variant).tb) {
+        name = "tb2_" + std::to_string(kTB2TileX) + "x" + std::to_string(kTB2TileY) + "_t" +
+               std::to_string(kTB2Threads) + "_zc" + std::to_string(variant_of(variant).zc);
     } else {
         const Variant v = variant_of(variant);
         name = "zmarch_" + std::to_string(tile_tx(v.cfg)) + "x" + std::to_string(tile_ty(v.cfg)) + "_t" +
@@ -1146,8 +1266,10 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     const int nf = p->batch ? 3 : (wave ? 3 : 2);
     for (size_t i = 0; i < Ls.size(); i++)
         for (int k = 0; k < (p->batch ? 3 : (wave ? 3 : 1)); k++) ST_TRY(check_ptr(fields[i * nf + k], "field"));
+    // scratch outputs (two for the temporally blocked sweep)
     int64_t scratch_bytes = 0;
     for (const Layout* L : Ls) scratch_bytes += round_up(L->bytes, 256);
+    if (!p->batch) scratch_bytes *= 2;
     void* scratch = nullptr;
     HIP_TRY(hipMalloc(&scratch, (size_t)scratch_bytes));
     hipEvent_t e0, e1;
@@ -1181,6 +1303,22 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             if (st != STENCIL_OK) break;
         }
         auto launch = [&]() -> hipError_t {
+            if (var.tb) {
+                const Layout& L = p->L;
+                TBView t{};
+                t.u = views[0].u;
+                t.prev = views[0].prev;
+                t.beta = views[0].beta;
+                t.out1 = views[0].out;
+                t.out2 = (char*)views[0].out + round_up(L.bytes, 256);
+                t.g = L.g;
+                t.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
+                t.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
+                t.zc = std::max(1, std::min(var.zc, L.g.n[0]));
+                t.nzc = (L.g.n[0] + t.zc - 1) / t.zc;
+                t.range = (uint32_t)L.bytes;
+                return launch_tb2(p->dtype, t, p->w, 0, -1, -1, s);
+            }
             if (p->batch)
                 return launch_zmarch_batch(p->radius, p->dtype, var.cfg, (const ZView*)vt.buf.p, (const int*)bs.buf.p,
                                            (int)views.size(), bst.back(), p->w, 0, 0, -1, s);
@@ -1209,6 +1347,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             st = fail(STENCIL_E_DEVICE, std::string("tuning launch: ") + hipGetErrorString(e));
             break;
         }
+        if (var.tb) ms *= 0.5f;   // one launch advances two steps
         if (ms < best_ms) {
             best_ms = ms;
             best = var_i;

@@ -126,9 +126,14 @@ def test_product_weights_equal_oracle_derivation():
 def test_variants_are_listed():
     p = S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8))
     n = p.variant_count()
-    assert n == 17
+    assert n == 20   # point, 16 z-marching, 3 temporally blocked
     names = [p.variant_name(v) for v in range(n)]
     assert names[0] == "point" and len(set(names)) == n
+    assert [x for x in names if x.startswith("tb2_")] == names[17:]
+    # temporal blocking covers the radius-4 wave with the zero halo only
+    assert S.Plan(S.WAVE2, (64, 64, 64), 2, S.second_derivative_weights(4)).variant_count() == 17
+    assert S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8),
+                  bc=S.BC_PERIODIC).variant_count() == 17
     p2 = S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2))
     assert p2.variant_count() == 1 and p2.variant == 0
     with pytest.raises(S.StencilError):
