@@ -244,6 +244,128 @@ def bench_batch(S, W, steps):
             "variant": bp.variant}
 
 
+def bench_heat2d(S, W, steps):
+    """2D 5-point heat, 256^2, Dirichlet zero halo, 100 steps: a field of
+    260 KiB stays in L2, so this measures launch and synchronisation cost
+    per step (one graph of 100 launches), not HBM bandwidth."""
+    H = W.heat2d_c1()
+    plan = S.Plan(S.HEAT, H.shape, 1, S.heat_weights(2, H.alpha), halo=1)
+    f = [plan.field() for _ in range(2)]
+    u0 = W.embed(W.round_to_storage(H.u0, "f32"), 1)
+    f[0].load(u0)
+    plan.run(f, H.nsteps)
+    with Timer() as t:
+        for _ in range(steps):
+            plan.run(f, H.nsteps)
+    ms = t.ms / steps
+    pts = float(np.prod(H.shape)) * H.nsteps
+    return {"interior": list(H.shape), "steps": H.nsteps, "GPts_s": round(pts / (ms * 1e-3) / 1e9, 2),
+            "ms_per_run": round(ms, 4), "us_per_step": round(ms * 1e3 / H.nsteps, 2),
+            "bound": "launch latency (field resident in L2)", "variant": plan.variant_name(plan.variant)}
+
+
+def bench_slab_share(S, W, steps):
+    """One GPU's share of the 512^3 wave split over 8 GPUs as z-slabs: a
+    64 x 512 x 512 interior (the slab z = 224..287 of the headline model, with
+    its source).  Every step first refreshes the two 4-plane z halos of u^n by
+    packing the faces and unpacking them into the halos (this slab's own
+    faces stand in for its neighbours'), then sweeps once.  The 400 steps of
+    pack, unpack and sweep are captured in one graph; the sweep alone over
+    the same slab is timed beside it."""
+    import torch
+    P = W.wave3d_c3(nsteps=400)
+    z0, nz = 224, 64
+    shape = (nz, 512, 512)
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    f[2].load(W.embed(W.round_to_storage(P.beta[z0:z0 + nz], "f32"), 4))
+    src = np.array([[P.src[0][0] - z0, P.src[0][1], P.src[0][2]]])
+    amp = torch.from_numpy(P.src_amp).cuda()
+    ex = plan.exchanges([8, 1, 1], [3, 0, 0])
+    buf = torch.empty(plan.exchange_elems(ex), dtype=torch.float32, device="cuda")
+    n = P.nsteps
+
+    def exchange_and_sweep():
+        for t in range(n):
+            plan.pack(f[0], ex, buf)
+            plan.unpack(f[0], ex, buf)
+            plan.run(f, 1, src=src, src_amp=amp[t:t + 1])
+
+    def reset():
+        f[0].storage.zero_()
+        f[1].storage.zero_()
+
+    reset()
+    exchange_and_sweep()
+    torch.cuda.synchronize()
+    eager = f[0].storage.clone()
+    mode = "graph"
+    try:
+        g = torch.cuda.CUDAGraph()
+        reset()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            exchange_and_sweep()
+        replays_equal = True
+        for _ in range(2):
+            reset()
+            g.replay()
+            torch.cuda.synchronize()
+            replays_equal &= bool(torch.equal(f[0].storage, eager))
+        run_once = g.replay
+    except Exception as e:  # capture unsupported: time the eager loop
+        log(f"[bench] slab graph capture failed ({e}); timing eager launches")
+        mode, replays_equal, run_once = "eager", None, exchange_and_sweep
+    with Timer() as t:
+        for _ in range(steps):
+            reset()
+            run_once()
+    ms_x = t.ms / steps
+    plan.tune(f, reps=2)
+    reset()
+    plan.run(f, n, src=src, src_amp=amp)
+    with Timer() as t:
+        for _ in range(steps):
+            reset()
+            plan.run(f, n, src=src, src_amp=amp)
+    ms_s = t.ms / steps
+    pts = float(np.prod(shape)) * n
+    face_mib = plan.exchange_elems(ex) * 4 / 2 ** 20
+    return {"interior": list(shape), "steps": n, "launches": mode,
+            "GPts_s_with_exchange": round(pts / (ms_x * 1e-3) / 1e9, 2), "ms_with_exchange": round(ms_x, 2),
+            "GPts_s_sweep_only": round(pts / (ms_s * 1e-3) / 1e9, 2), "ms_sweep_only": round(ms_s, 2),
+            "sweep_only_variant": plan.variant_name(plan.variant),
+            "exchange_us_per_step": round((ms_x - ms_s) * 1e3 / n, 2),
+            "faces_MiB_per_step": round(face_mib, 2), "graph_replays_equal_eager": replays_equal}
+
+
+def bench_faces(S, W, reps=20):
+    """Pack and unpack throughput of the halo faces of a 512^3 FP32 field
+    (halo 4): the z faces are contiguous planes, the y faces 2 KiB row runs,
+    the x faces 16-byte runs.  Bytes = elements x 4 B read + written."""
+    import torch
+    plan = S.Plan(S.WAVE2, (512, 512, 512), 4, S.second_derivative_weights(8), halo=4)
+    f = plan.field()
+    allx = plan.exchanges([1, 1, 1], [0, 0, 0], periodic=True)
+    out = {}
+    for d, name in enumerate(("z", "y", "x")):
+        ex = [e for e in allx if e.size[d] == 4]
+        buf = torch.empty(plan.exchange_elems(ex), dtype=torch.float32, device="cuda")
+        nb = 2.0 * plan.exchange_elems(ex) * 4
+        plan.pack(f, ex, buf)
+        with Timer() as t:
+            for _ in range(reps):
+                plan.pack(f, ex, buf)
+        pk = nb / (t.ms / reps * 1e-3) / 1e9
+        with Timer() as t:
+            for _ in range(reps):
+                plan.unpack(f, ex, buf)
+        up = nb / (t.ms / reps * 1e-3) / 1e9
+        out[f"{name}_faces"] = {"MiB": round(plan.exchange_elems(ex) * 4 / 2 ** 20, 2),
+                                "pack_GBps": round(pk, 1), "unpack_GBps": round(up, 1)}
+    return out
+
+
 def bench_adjoint(S, W, steps):
     """Checkpointed gradient of J = 1/2 |d|^2 (the adjoint's work does not
     depend on the residual values) vs the plain forward of the same model."""
@@ -381,6 +503,14 @@ def main():
                                 "frac_hbm_8B": round(hg * 8 / HBM_PEAK_GBS, 4),
                                 "variant": hp.variant_name(hp.variant)}
         del hf
+        torch.cuda.empty_cache()
+        log("[bench] heat 2D 256^2 x 100")
+        extras["heat2d_so2"] = bench_heat2d(S, W, 20)
+        log("[bench] one GPU's z-slab share with halo exchange")
+        extras["slab_share_exchange"] = bench_slab_share(S, W, max(1, args.steps // 2))
+        torch.cuda.empty_cache()
+        log("[bench] face pack/unpack")
+        extras["halo_faces"] = bench_faces(S, W)
         torch.cuda.empty_cache()
         if not args.no_batch:
             log("[bench] batched shots")
