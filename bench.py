@@ -241,7 +241,8 @@ def bench_batch(S, W, steps):
             "ms_per_run": round(ms_b, 2), "sequential_GPts_s": round(pts / (ms_s * 1e-3) / 1e9, 2),
             "sequential_ms": round(ms_s, 2), "batched_vs_sequential": round(ms_s / ms_b, 3),
             "bitwise_equal_to_sequential": bool(same),
-            "variant": bp.variant}
+            "variant": bp.variant_name(bp.variant),
+            "sequential_variants": sorted({p.variant_name(p.variant) for p, _ in plans})}
 
 
 def bench_heat2d(S, W, steps):

@@ -335,6 +335,11 @@ class BatchPlan:
         call("stencil_variant_count", self._h, C.byref(n))
         return n.value
 
+    def variant_name(self, v: int) -> str:
+        buf = C.create_string_buffer(64)
+        call("stencil_variant_name", self._h, int(v), buf, 64)
+        return buf.value.decode()
+
     def tune(self, fields: list, reps: int = 2, stream=None) -> int:
         flat = [f.ptr for shot in fields for f in shot]
         ptrs = (C.c_void_p * len(flat))(*flat)

@@ -190,23 +190,19 @@ hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tb2(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p,
-                      hipStream_t s) {
-    switch (dtype) {
-        case DT_F32: return tb2_f32(v, w, arow, trow_u, trow_p, s);
-        case DT_BF16: return tb2_bf16(v, w, arow, trow_u, trow_p, s);
-        case DT_F16: return tb2_f16(v, w, arow, trow_u, trow_p, s);
-    }
+hipError_t launch_tb2(int mode, int radius, int dtype, const TBView& v, const Coefs& w, int arow, int trow_u,
+                      int trow_p, hipStream_t s) {
+    if (mode == MODE_WAVE && radius == 4) return tb2_wave(dtype, v, w, arow, trow_u, trow_p, s);
+    if (mode == MODE_HEAT && dtype == DT_F32) return tb2_heat_f32(radius, v, w, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_start,
-                               int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
-                               hipStream_t s) {
+hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_map,
+                               int nblocks, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
     switch (dtype) {
-        case DT_F32: return zmarch_batch_f32(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
-        case DT_BF16: return zmarch_batch_bf16(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
-        case DT_F16: return zmarch_batch_f16(radius, cfg, d_views, d_block_start, nshots, nblocks, w, parity, arow, trow, s);
+        case DT_F32: return zmarch_batch_f32(radius, cfg, d_views, d_block_map, nblocks, w, parity, arow, trow, s);
+        case DT_BF16: return zmarch_batch_bf16(radius, cfg, d_views, d_block_map, nblocks, w, parity, arow, trow, s);
+        case DT_F16: return zmarch_batch_f16(radius, cfg, d_views, d_block_map, nblocks, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }

@@ -121,9 +121,9 @@ hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const C
                         hipStream_t s);
 hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& v, const Coefs& w,
                          int parity, int arow, int trow, hipStream_t s);
-hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_start,
-                               int nshots, int nblocks, const Coefs& w, int parity, int arow, int trow,
-                               hipStream_t s);
+// batched shots: d_block_map[2 b], d_block_map[2 b + 1] = shot and block within the shot of block b
+hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_map,
+                               int nblocks, const Coefs& w, int parity, int arow, int trow, hipStream_t s);
 // per-storage-type instantiations (zmarch_*.hip)
 hipError_t zmarch_fwd_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
                           int trow, hipStream_t s);
@@ -133,19 +133,22 @@ hipError_t zmarch_fwd_f16(int mode, int radius, int cfg, const ZView& v, const C
                           int trow, hipStream_t s);
 hipError_t zmarch_adj_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
                           int trow, hipStream_t s);
-hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                            const Coefs& w, int parity, int arow, int trow, hipStream_t s);
-hipError_t zmarch_batch_bf16(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                             const Coefs& w, int parity, int arow, int trow, hipStream_t s);
-hipError_t zmarch_batch_f16(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                            const Coefs& w, int parity, int arow, int trow, hipStream_t s);
-// depth-2 temporal blocking (radius 4, wave): steps arow and arow + 1;
-// receivers record u^n as row trow_u and u^{n-1} as row trow_p (if >= 0)
-hipError_t launch_tb2(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p,
-                      hipStream_t s);
-hipError_t tb2_f32(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
-hipError_t tb2_bf16(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
-hipError_t tb2_f16(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
+hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* bmap, int nblocks, const Coefs& w,
+                            int parity, int arow, int trow, hipStream_t s);
+hipError_t zmarch_batch_bf16(int radius, int cfg, const ZView* views, const int* bmap, int nblocks, const Coefs& w,
+                             int parity, int arow, int trow, hipStream_t s);
+hipError_t zmarch_batch_f16(int radius, int cfg, const ZView* views, const int* bmap, int nblocks, const Coefs& w,
+                            int parity, int arow, int trow, hipStream_t s);
+// Depth-2 temporal blocking.  Wave (radius 4): steps arow and arow + 1;
+// receivers record u^n as row trow_u and u^{n-1} as row trow_p (if >= 0).
+// Heat (radius 1..4, FP32): u^{n+2} from u^n into out2.
+hipError_t launch_tb2(int mode, int radius, int dtype, const TBView& v, const Coefs& w, int arow, int trow_u,
+                      int trow_p, hipStream_t s);
+hipError_t tb2_wave(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
+hipError_t tb2_heat_f32(int radius, const TBView& v, const Coefs& w, hipStream_t s);
+// batched shots: d_views[nshots] (device), d_block_map as for launch_zmarch_batch
+hipError_t tb2_batch(int dtype, const TBView* d_views, const int* d_block_map, int nblocks, const Coefs& w, int arow,
+                     int trow_u, int trow_p, hipStream_t s);
 // tile shape, threads and z-chunk lengths of the temporally blocked sweep
 inline constexpr int kTB2TileX = 64, kTB2TileY = 32, kTB2Threads = 768;
 inline constexpr int kTB2ZChunks[] = {256, 128, 64};

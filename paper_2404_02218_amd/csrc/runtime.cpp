@@ -225,8 +225,13 @@ struct stencil_plan_s {
     // batch
     std::vector<Layout> shots;
     std::vector<PointTables> shot_src, shot_rec;
-    DevTable views, block_start;
+    DevTable views, block_map;   // block_map: (shot, block within the shot) per workgroup
     std::vector<int> bstart;
+    // batched temporal blocking: per-shot extended source lists, the second
+    // field pair of every shot, and the view tables of even and odd passes
+    std::vector<PointTables> shot_src_ext;
+    std::vector<DevBuf> shot_tb;   // 2 per shot
+    DevTable tbviews[2];
 
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -243,17 +248,25 @@ stencil_status check_plan(stencil_plan p, bool want_batch) {
     return STENCIL_OK;
 }
 
-// The depth-2 temporally blocked sweep covers the 3D radius-4 wave with the
-// zero halo.  Its loads start 8 elements left of a tile and address a field
-// with 32-bit byte offsets.
+// The depth-2 temporally blocked sweep covers the 3D radius-4 wave (any
+// storage type) and the 3D heat (FP32), with the zero halo.  Its loads start
+// 8 elements left of a tile and address a field with 32-bit byte offsets.
 bool tb_supported(const stencil_plan_s* p) {
-    if (p->batch || p->ndim != 3 || p->kind != STENCIL_WAVE2 || p->radius != 4 || p->bc != STENCIL_BC_DIRICHLET0)
-        return false;
-    return p->L.g.xlead >= 8 && p->L.bytes < (int64_t(1) << 31);
+    if (p->batch || p->ndim != 3 || p->bc != STENCIL_BC_DIRICHLET0) return false;
+    const bool wave = p->kind == STENCIL_WAVE2 && p->radius == 4;
+    const bool heat = p->kind == STENCIL_HEAT && p->dtype == STENCIL_F32;
+    return (wave || heat) && p->L.g.xlead >= 8 && p->L.bytes < (int64_t(1) << 31);
+}
+
+bool tb_batch_supported(const stencil_plan_s* p) {
+    if (!p->batch || p->radius != 4) return false;
+    for (const Layout& L : p->shots)
+        if (L.g.xlead < 8 || L.bytes >= (int64_t(1) << 31)) return false;
+    return true;
 }
 
 int variant_count_of(const stencil_plan_s* p) {
-    if (p->batch) return kNumZVariants + 1;
+    if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
     if (p->ndim != 3) return 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
 }
@@ -365,12 +378,19 @@ RecList rec_list(const PointTables& T, double* trace) {
     return r;
 }
 
+// z-chunks: as many as chunks of at most `zc` planes need, of equal length
+// (a short last chunk would pay the 2r warm-up planes for a few outputs)
+void chunking(int nz, int zc, int& len, int& count) {
+    const int c = std::max(1, std::min(zc, std::max(1, nz)));
+    count = (nz + c - 1) / c;
+    len = count > 0 ? (nz + count - 1) / count : c;
+}
+
 void set_tiling(ZView& v, const Layout& L, const Variant& var) {
     const int TX = tile_tx(var.cfg), TY = tile_ty(var.cfg);
     v.ntx = (L.g.n[2] + TX - 1) / TX;
     v.nty = (L.g.n[1] + TY - 1) / TY;
-    v.zc = std::max(1, std::min(var.zc, std::max(1, L.g.n[0])));
-    v.nzc = (L.g.n[0] + v.zc - 1) / v.zc;
+    chunking(L.g.n[0], var.zc, v.zc, v.nzc);
     if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) v.ntx = v.nty = v.nzc = 0;
 }
 
@@ -474,15 +494,14 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
         v.g = L.g;
         v.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
         v.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
-        v.zc = std::max(1, std::min(var.zc, L.g.n[0]));
-        v.nzc = (L.g.n[0] + v.zc - 1) / v.zc;
+        chunking(L.g.n[0], var.zc, v.zc, v.nzc);
         v.src_t = st;
         v.src_e = se;
         v.rec = rl;
         v.range = (uint32_t)L.bytes;
         const int tu = (rl.n > 0 && k >= 1) ? (int)(2 * k - 1) : -1;
         const int tp = (rl.n > 0 && k >= 1) ? (int)(2 * k - 2) : -1;
-        HIP_TRY(launch_tb2(p->dtype, v, p->w, (int)(2 * k), tu, tp, s));
+        HIP_TRY(launch_tb2(MODE_WAVE, p->radius, p->dtype, v, p->w, (int)(2 * k), tu, tp, s));
         newest = dst[0];
         prev = dst[1];
     }
@@ -512,15 +531,36 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
 stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, int64_t nsteps,
                            const stencil_source* src, const stencil_receivers* rec, hipStream_t s) {
     const Layout& L = p->L;
-    const Variant var = variant_of(p->variant);
-    if (var.tb) return enqueue_run_tb(p, var, a, b, beta, nsteps, src, rec, s);
+    Variant var = variant_of(p->variant);
     const bool wave = p->kind == STENCIL_WAVE2;
+    if (var.tb && wave) return enqueue_run_tb(p, var, a, b, beta, nsteps, src, rec, s);
+    int64_t t0 = 0;
+    if (var.tb) {
+        // heat: an even number of two-step passes from one buffer into the
+        // other (so u^{2K} is back in a), then plain sweeps on the same tiles
+        int64_t passes = nsteps / 2;
+        if (passes & 1) passes--;
+        TBView v{};
+        v.g = L.g;
+        v.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
+        v.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
+        chunking(L.g.n[0], var.zc, v.zc, v.nzc);
+        v.range = (uint32_t)L.bytes;
+        for (int64_t k = 0; k < passes; k++) {
+            v.u = (k & 1) ? b : a;
+            v.out2 = (k & 1) ? a : b;
+            HIP_TRY(launch_tb2(MODE_HEAT, p->radius, p->dtype, v, p->w, 0, -1, -1, s));
+        }
+        t0 = 2 * passes;
+        var.tb = false;
+        var.zmarch = true;
+    }
     const int mode = wave ? MODE_WAVE : MODE_HEAT;
     const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
     const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
     std::vector<CopyList> per;
     if (p->bc == STENCIL_BC_PERIODIC) periodic_copies(L, p->radius, per);
-    for (int64_t t = 0; t < nsteps; t++) {
+    for (int64_t t = t0; t < nsteps; t++) {
         const int parity = (int)(t & 1);
         void* cur = parity ? b : a;
         void* nxt = parity ? a : b;
@@ -725,7 +765,7 @@ stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const 
     void* a = fields[0];
     void* b = fields[1];
     const void* beta = p->kind == STENCIL_WAVE2 ? fields[2] : nullptr;
-    if (variant_of(p->variant).tb) ST_TRY(ensure_tb_pair(p));
+    if (variant_of(p->variant).tb && p->kind == STENCIL_WAVE2) ST_TRY(ensure_tb_pair(p));
     if (nsteps >= 2 && graphs_enabled()) {
         std::vector<int64_t> key = {(int64_t)(uintptr_t)a,
                                     (int64_t)(uintptr_t)b,
@@ -873,6 +913,8 @@ stencil_status stencil_batch_create(stencil_plan* out, int nshots, const int64_t
     }
     p->shot_src.resize(nshots);
     p->shot_rec.resize(nshots);
+    p->shot_src_ext.resize(nshots);
+    p->shot_tb.resize(2 * (size_t)nshots);
     // default: the 64x32 tile with 64-plane chunks
     p->variant = 1 + 2 * kNumTileCfgs + 0;
     *out = p;
@@ -884,6 +926,18 @@ stencil_status stencil_batch_layout(stencil_plan p, int shot, int64_t* extents, 
     ST_TRY(check_plan(p, true));
     if (shot < 0 || shot >= (int)p->shots.size()) return fail(STENCIL_E_INVALID, "shot index out of range");
     return layout_out(p->shots[shot], extents, strides, offset, bytes);
+}
+
+// (shot, block within the shot) for every workgroup of a batched launch,
+// from the prefix sum of the shots' workgroup counts
+static stencil_status upload_block_map(const std::vector<int>& bstart, DevTable& table) {
+    std::vector<int> map(2 * (size_t)std::max(1, bstart.back()), 0);
+    for (size_t sh = 0; sh + 1 < bstart.size(); sh++)
+        for (int b = bstart[sh]; b < bstart[sh + 1]; b++) {
+            map[2 * (size_t)b] = (int)sh;
+            map[2 * (size_t)b + 1] = b - bstart[sh];
+        }
+    return table.upload(map.data(), sizeof(int) * map.size());
 }
 
 static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
@@ -903,6 +957,7 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
         const stencil_source* ss = src ? &src[s] : nullptr;
         const stencil_receivers* rr = rec ? &rec[s] : nullptr;
         ST_TRY(build_points(L, ss ? ss->n : 0, ss ? ss->pos : nullptr, var.cfg, p->shot_src[s]));
+        if (var.tb) ST_TRY(build_points(L, ss ? ss->n : 0, ss ? ss->pos : nullptr, var.cfg, p->shot_src_ext[s], 4));
         ST_TRY(build_points(L, rr ? rr->n : 0, rr ? rr->pos : nullptr, -1, p->shot_rec[s]));
         v.src = src_list(p->shot_src[s], ss ? ss->amp : nullptr, nullptr);
         v.rec = rec_list(p->shot_rec[s], rr ? rr->trace : nullptr);
@@ -912,7 +967,43 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
     }
     (void)nsteps;
     ST_TRY(p->views.upload(views.data(), sizeof(ZView) * views.size()));
-    ST_TRY(p->block_start.upload(p->bstart.data(), sizeof(int) * p->bstart.size()));
+    ST_TRY(upload_block_map(p->bstart, p->block_map));
+    if (var.tb) {
+        // pass k reads pair k & 1 (newest, previous) and writes the other pair
+        // (u^{n+2} into its first buffer, u^{n+1} into its second)
+        std::vector<TBView> tv[2];
+        for (int s = 0; s < ns; s++) {
+            const Layout& L = p->shots[s];
+            const size_t bytes = (size_t)L.bytes;
+            for (int k = 0; k < 2; k++) {
+                DevBuf& d = p->shot_tb[2 * s + k];
+                if (d.p && d.cap >= bytes) continue;
+                ST_TRY(d.ensure(bytes));
+                HIP_TRY(hipMemset(d.p, 0, d.cap));
+                HIP_TRY(hipDeviceSynchronize());
+            }
+            void* pr[2][2] = {{fields[3 * s], fields[3 * s + 1]}, {p->shot_tb[2 * s].p, p->shot_tb[2 * s + 1].p}};
+            for (int par = 0; par < 2; par++) {
+                TBView t{};
+                t.u = pr[par][0];
+                t.prev = pr[par][1];
+                t.beta = fields[3 * s + 2];
+                t.out2 = pr[1 - par][0];
+                t.out1 = pr[1 - par][1];
+                t.g = L.g;
+                t.ntx = views[s].ntx;
+                t.nty = views[s].nty;
+                t.zc = views[s].zc;
+                t.nzc = views[s].nzc;
+                t.src_t = views[s].src;
+                t.src_e = src_list(p->shot_src_ext[s], views[s].src.amp, nullptr);
+                t.rec = views[s].rec;
+                t.range = (uint32_t)L.bytes;
+                tv[par].push_back(t);
+            }
+        }
+        for (int par = 0; par < 2; par++) ST_TRY(p->tbviews[par].upload(tv[par].data(), sizeof(TBView) * tv[par].size()));
+    }
     return STENCIL_OK;
 }
 
@@ -920,10 +1011,30 @@ static stencil_status enqueue_batch(stencil_plan p, const std::vector<ZView>& vi
                                     bool any_rec, hipStream_t s) {
     const int ns = (int)p->shots.size();
     const int nblocks = p->bstart[ns];
-    for (int64_t t = 0; t < nsteps; t++) {
+    int64_t t0 = 0;
+    if (var.tb) {
+        // an even number of two-step passes (as in a single-plan run), then
+        // plain batched sweeps on the 64 x 32 tiles for the rest
+        int64_t passes = nsteps / 2;
+        if (passes & 1) passes--;
+        for (int64_t k = 0; k < passes; k++) {
+            const int tu = (any_rec && k >= 1) ? (int)(2 * k - 1) : -1;
+            const int tp = (any_rec && k >= 1) ? (int)(2 * k - 2) : -1;
+            HIP_TRY(tb2_batch(p->dtype, (const TBView*)p->tbviews[k & 1].buf.p, (const int*)p->block_map.buf.p, nblocks,
+                              p->w, (int)(2 * k), tu, tp, s));
+        }
+        if (any_rec && passes > 0) {
+            for (int sh = 0; sh < ns; sh++) {
+                const ZView& v = views[sh];
+                if (v.rec.n > 0) HIP_TRY(launch_record(p->dtype, v.prev, v.g, v.rec, (int)(2 * passes - 2), s));
+            }
+        }
+        t0 = 2 * passes;
+    }
+    for (int64_t t = t0; t < nsteps; t++) {
         const int trow = (any_rec && t >= 1) ? (int)(t - 1) : -1;
         HIP_TRY(launch_zmarch_batch(p->radius, p->dtype, var.cfg, (const ZView*)p->views.buf.p,
-                                    (const int*)p->block_start.buf.p, ns, nblocks, p->w, (int)(t & 1), (int)t, trow, s));
+                                    (const int*)p->block_map.buf.p, nblocks, p->w, (int)(t & 1), (int)t, trow, s));
     }
     if (any_rec && nsteps > 0) {
         for (int sh = 0; sh < ns; sh++) {
@@ -962,7 +1073,9 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
     ST_TRY(batch_prepare(p, fields, nsteps, src, rec, var, views));
     hipStream_t s = (hipStream_t)stream;
     if (nsteps >= 2 && graphs_enabled()) {
-        std::vector<int64_t> key = {nsteps, p->variant, (int64_t)(uintptr_t)p->views.buf.p, any_rec};
+        std::vector<int64_t> key = {nsteps, p->variant, (int64_t)(uintptr_t)p->views.buf.p, any_rec,
+                                    (int64_t)(uintptr_t)p->block_map.buf.p,
+                                    (int64_t)(uintptr_t)p->tbviews[0].buf.p, (int64_t)(uintptr_t)p->tbviews[1].buf.p};
         for (const ZView& v : views) {
             key.push_back((int64_t)(uintptr_t)v.u);
             key.push_back((int64_t)(uintptr_t)v.prev);
@@ -1269,7 +1382,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     // scratch outputs (two for the temporally blocked sweep)
     int64_t scratch_bytes = 0;
     for (const Layout* L : Ls) scratch_bytes += round_up(L->bytes, 256);
-    if (!p->batch) scratch_bytes *= 2;
+    scratch_bytes *= 2;
     void* scratch = nullptr;
     HIP_TRY(hipMalloc(&scratch, (size_t)scratch_bytes));
     hipEvent_t e0, e1;
@@ -1278,7 +1391,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     int best = p->variant;
     float best_ms = 1e30f;
     stencil_status st = STENCIL_OK;
-    DevTable vt, bs;
+    DevTable vt, bs, tvt;
     for (int var_i = p->batch ? 1 : 0; var_i < nvar && st == STENCIL_OK; var_i++) {
         const Variant var = variant_of(var_i);
         std::vector<ZView> views;
@@ -1293,16 +1406,40 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             v.out = (char*)scratch + off;
             off += round_up(L.bytes, 256);
             v.g = L.g;
-            if (var.zmarch) set_tiling(v, L, var);
+            if (var.zmarch || var.tb) set_tiling(v, L, var);
             views.push_back(v);
             bst.push_back(bst.back() + (int)zmarch_blocks(v));
         }
         if (p->batch) {
             st = vt.upload(views.data(), sizeof(ZView) * views.size());
-            if (st == STENCIL_OK) st = bs.upload(bst.data(), sizeof(int) * bst.size());
+            if (st == STENCIL_OK) st = upload_block_map(bst, bs);
+            if (st == STENCIL_OK && var.tb) {
+                std::vector<TBView> tv;
+                int64_t o2 = off;
+                for (size_t i = 0; i < Ls.size(); i++) {
+                    const Layout& L = *Ls[i];
+                    TBView t{};
+                    t.u = views[i].u;
+                    t.prev = views[i].prev;
+                    t.beta = views[i].beta;
+                    t.out1 = views[i].out;
+                    t.out2 = (char*)scratch + o2;
+                    o2 += round_up(L.bytes, 256);
+                    t.g = L.g;
+                    t.ntx = views[i].ntx;
+                    t.nty = views[i].nty;
+                    t.zc = views[i].zc;
+                    t.nzc = views[i].nzc;
+                    t.range = (uint32_t)L.bytes;
+                    tv.push_back(t);
+                }
+                st = tvt.upload(tv.data(), sizeof(TBView) * tv.size());
+            }
             if (st != STENCIL_OK) break;
         }
         auto launch = [&]() -> hipError_t {
+            if (var.tb && p->batch)
+                return tb2_batch(p->dtype, (const TBView*)tvt.buf.p, (const int*)bs.buf.p, bst.back(), p->w, 0, -1, -1, s);
             if (var.tb) {
                 const Layout& L = p->L;
                 TBView t{};
@@ -1314,14 +1451,13 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
                 t.g = L.g;
                 t.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
                 t.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
-                t.zc = std::max(1, std::min(var.zc, L.g.n[0]));
-                t.nzc = (L.g.n[0] + t.zc - 1) / t.zc;
+                chunking(L.g.n[0], var.zc, t.zc, t.nzc);
                 t.range = (uint32_t)L.bytes;
-                return launch_tb2(p->dtype, t, p->w, 0, -1, -1, s);
+                return launch_tb2(mode, p->radius, p->dtype, t, p->w, 0, -1, -1, s);
             }
             if (p->batch)
                 return launch_zmarch_batch(p->radius, p->dtype, var.cfg, (const ZView*)vt.buf.p, (const int*)bs.buf.p,
-                                           (int)views.size(), bst.back(), p->w, 0, 0, -1, s);
+                                           bst.back(), p->w, 0, 0, -1, s);
             if (var.zmarch) return launch_zmarch(mode, p->radius, p->dtype, var.cfg, views[0], p->w, 0, 0, -1, s);
             Box3 box{};
             for (int a = 0; a < 3; a++) {

@@ -368,23 +368,18 @@ __global__ __launch_bounds__(BX* BY) void k_zmarch(ZView v, Coefs w, int parity,
     zmarch_tile<MODE, R, T, BX, BY, VY, VX, NTH>(v, w, lb, parity, arow, trow, lds);
 }
 
+// Batched shots: block_map[2 lb], block_map[2 lb + 1] = shot and block within
+// the shot of logical block lb (one load instead of a search over the
+// shots' block counts, whose dependent loads would delay every workgroup).
 template <int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict__ views,
-                                                        const int* __restrict__ block_start, int nshots,
-                                                        Coefs w, int parity, int arow, int trow) {
+                                                        const int* __restrict__ block_map, Coefs w, int parity,
+                                                        int arow, int trow) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    // shot owning logical block lb: block_start is the prefix sum of blocks per shot
-    int lo = 0, hi = nshots - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (block_start[mid] <= lb)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const ZView v = views[lo];
-    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, lb - block_start[lo], parity, arow, trow, lds);
+    const int shot = block_map[2 * lb], local = block_map[2 * lb + 1];
+    const ZView v = views[shot];
+    zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, local, parity, arow, trow, lds);
 }
 
 // dynamic LDS above 64 KiB must be enabled per kernel once
@@ -432,28 +427,27 @@ static hipError_t zm_r(int radius, int cfg, const ZView& v, const Coefs& w, int 
 }
 
 template <int R, typename T, int C>
-static hipError_t zb_launch(const ZView* views, const int* bs, int nshots, int nblocks, const Coefs& w,
-                            int parity, int arow, int trow, hipStream_t s) {
+static hipError_t zb_launch(const ZView* views, const int* bmap, int nblocks, const Coefs& w, int parity, int arow,
+                            int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
     constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     if (nblocks == 0) return hipSuccess;
     auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(k, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(c.bx * c.by), lds, s, views, bs, nshots, w, parity, arow,
-                       trow);
+    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(c.bx * c.by), lds, s, views, bmap, w, parity, arow, trow);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                         const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
+static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bmap, int nblocks, const Coefs& w,
+                         int parity, int arow, int trow, hipStream_t s) {
     if (radius != 4) return hipErrorInvalidValue;
     switch (cfg) {
-        case 0: return zb_launch<4, T, 0>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 1: return zb_launch<4, T, 1>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 2: return zb_launch<4, T, 2>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
-        case 3: return zb_launch<4, T, 3>(views, bs, nshots, nblocks, w, parity, arow, trow, s);
+        case 0: return zb_launch<4, T, 0>(views, bmap, nblocks, w, parity, arow, trow, s);
+        case 1: return zb_launch<4, T, 1>(views, bmap, nblocks, w, parity, arow, trow, s);
+        case 2: return zb_launch<4, T, 2>(views, bmap, nblocks, w, parity, arow, trow, s);
+        case 3: return zb_launch<4, T, 3>(views, bmap, nblocks, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }

@@ -8,9 +8,9 @@ hipError_t zmarch_fwd_f32(int mode, int radius, int cfg, const ZView& v, const C
     return zmarch_modes<float>(mode, radius, cfg, v, w, parity, arow, trow, s);
 }
 
-hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* bs, int nshots, int nblocks,
-                           const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
-    return zb_cfg<float>(radius, cfg, views, bs, nshots, nblocks, w, parity, arow, trow, s);
+hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* bmap, int nblocks,
+                            const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
+    return zb_cfg<float>(radius, cfg, views, bmap, nblocks, w, parity, arow, trow, s);
 }
 
 }  // namespace stn

@@ -1,7 +1,9 @@
-// Temporal blocking of depth 2 for the radius-4 wave sweep: one launch
-// advances the leapfrog by two steps.  It reads u^n, u^{n-1} and beta once and
-// writes u^{n+1} and u^{n+2} to two other buffers, so a point-update moves
-// 10 bytes of FP32 storage instead of 16.
+// Temporal blocking of depth 2: one launch advances a sweep by two steps.
+//  * radius-4 wave: reads u^n, u^{n-1} and beta once and writes u^{n+1} and
+//    u^{n+2} to two other buffers, so a point-update moves 10 bytes of FP32
+//    storage instead of 16;
+//  * heat (any radius up to 4): reads u^n and writes u^{n+2}, 4 bytes per
+//    point-update instead of 8.
 //
 // A workgroup owns a 64 x 32 tile of the xy plane and a z-chunk and marches up
 // the chunk.  Its first 512 threads (8 wavefronts) own one 4-point group of
@@ -35,8 +37,10 @@
 
 namespace stn {
 
+template <int R_, bool WAVE_>
 struct TB2 {
-    static constexpr int R = 4, Q = 2 * R + 1;
+    static constexpr int R = R_, Q = 2 * R + 1;
+    static constexpr bool WAVE = WAVE_;
     static constexpr int TX = 64, TY = 32;
     static constexpr int NTILE = (TX / 4) * TY;                       // 512 tile-role threads
     static constexpr int NRT = 256;                                   // ring-role threads
@@ -47,17 +51,23 @@ struct TB2 {
     static constexpr int NS1 = 2, NS2 = R + 1;   // NS2: u^{n+1} planes z1-R .. z1
     static constexpr int NRING = EG * EY - NTILE;                      // 208 ring groups
     static constexpr int NMX = 2 * EY, NMY = 2 * R * EG, NMARG = NMX + NMY;  // 224 margin groups
-    // LDS: NS1 u^n planes, NS2 u^{n+1} planes, and NS2 planes of the tile
-    // groups' own beta (each read back only by its thread)
-    static constexpr int LDS_FLOATS = NS1 * P1 + NS2 * P2 + NS2 * NTILE * 4;
+    // LDS: NS1 u^n planes, NS2 u^{n+1} planes, and (wave) NS2 planes of the
+    // tile groups' own beta (each read back only by its thread)
+    static constexpr int LDS_FLOATS = NS1 * P1 + NS2 * P2 + (WAVE ? NS2 * NTILE * 4 : 0);
+    static_assert(R >= 1 && R <= 4, "the x ring and margins are one 4-point group wide");
+    // waves per SIMD the register budget is sized for: the wave kernel needs
+    // its registers at one workgroup per CU (3 waves per SIMD); the heat
+    // kernel with r <= 2 fits two workgroups per CU (6 waves per SIMD)
+    static constexpr int WAVES_PER_SIMD = (!WAVE && R <= 2) ? 6 : 3;
     static_assert(NRING <= NRT && NMARG <= NRT, "one ring and one margin group per ring-role thread");
     static_assert(NTILE % 64 == 0 && NRT % 64 == 0, "roles split at wavefront boundaries");
 };
 
 // ring group k of E as (ex, ey): R rows above, R rows below, then the left
 // and right columns of the tile rows
+template <int R>
 __device__ static inline void tb2_ring_group(int k, int& ex, int& ey) {
-    using Z = TB2;
+    using Z = TB2<R, false>;
     constexpr int top = Z::EG * Z::R;
     if (k < top) {
         ey = k / Z::EG;
@@ -80,50 +90,43 @@ __device__ static inline void tb2_ring_group(int k, int& ex, int& ey) {
 // y taps from the rows above and below).  The four points advance through
 // the canonical order of each point's sum (centre, z pairs, y pairs, x pairs,
 // k = 1 .. R within an axis).
-template <class ZT>
+template <int R, int MODE, class ZT>
 __device__ __forceinline__ void tb2_star(const Coefs& w, ZT&& zt, const float* L, int W, const float4& prev,
                                          const float4& beta, float (&o)[4]) {
-    constexpr int R = TB2::R;
-    static_assert(R % 2 == 0, "pairs are taken two at a time");
     const float4 c = zt(R);
     float acc[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) acc[i] = w.cd0 * comp(c, i);
-    // taps at -k and +k for k = k0, k0 + 1 of one axis
-    auto block = [&](int k0, const float4& m0, const float4& p0, const float4& m1, const float4& p1) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            acc[i] = fmaf(w.c[k0], comp(m0, i) + comp(p0, i), acc[i]);
-            acc[i] = fmaf(w.c[k0 + 1], comp(m1, i) + comp(p1, i), acc[i]);
+    for (int k = 1; k <= R; k++) {
+        const float4 m = zt(R - k), p = zt(R + k);
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[i] = fmaf(w.c[k], comp(m, i) + comp(p, i), acc[i]);
+    }
+    if constexpr (MODE == MODE_HEAT) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 1; k <= R; k++) {
+        const float4 m = *reinterpret_cast<const float4*>(L - k * W);
+        const float4 p = *reinterpret_cast<const float4*>(L + k * W);
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[i] = fmaf(w.c[k], comp(m, i) + comp(p, i), acc[i]);
+        // the heat kernels run at 6 waves per SIMD: keep one pair of taps in
+        // registers at a time
+        if constexpr (MODE == MODE_HEAT) __builtin_amdgcn_sched_barrier(0);
+    }
+    const float4 xl = *reinterpret_cast<const float4*>(L - 4);
+    const float4 xr = *reinterpret_cast<const float4*>(L + 4);
+    const float xv[12] = {xl.x, xl.y, xl.z, xl.w, c.x, c.y, c.z, c.w, xr.x, xr.y, xr.z, xr.w};
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        float m[R], p[R];
+#pragma unroll
+        for (int k = 1; k <= R; k++) {
+            m[k - 1] = xv[4 + i - k];
+            p[k - 1] = xv[4 + i + k];
         }
-    };
-#pragma unroll
-    for (int k = 1; k <= R; k += 2) {
-        block(k, zt(R - k), zt(R + k), zt(R - k - 1), zt(R + k + 1));
-            }
-#pragma unroll
-    for (int k = 1; k <= R; k += 2) {
-        const float4 m0 = *reinterpret_cast<const float4*>(L - k * W);
-        const float4 p0 = *reinterpret_cast<const float4*>(L + k * W);
-        const float4 m1 = *reinterpret_cast<const float4*>(L - (k + 1) * W);
-        const float4 p1 = *reinterpret_cast<const float4*>(L + (k + 1) * W);
-        block(k, m0, p0, m1, p1);
-            }
-    {
-        const float4 xl = *reinterpret_cast<const float4*>(L - 4);
-        const float4 xr = *reinterpret_cast<const float4*>(L + 4);
-        const float xv[12] = {xl.x, xl.y, xl.z, xl.w, c.x, c.y, c.z, c.w, xr.x, xr.y, xr.z, xr.w};
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            float m[R], p[R];
-#pragma unroll
-            for (int k = 1; k <= R; k++) {
-                m[k - 1] = xv[4 + i - k];
-                p[k - 1] = xv[4 + i + k];
-            }
-            acc[i] = axis_sum<R>(acc[i], w, m, p);
-            o[i] = time_update<MODE_WAVE>(acc[i], comp(c, i), comp(prev, i), comp(beta, i));
-        }
+        acc[i] = axis_sum<R>(acc[i], w, m, p);
+        o[i] = time_update<MODE>(acc[i], comp(c, i), comp(prev, i), comp(beta, i));
     }
 }
 
@@ -207,18 +210,19 @@ __device__ __forceinline__ void tb2_store(__amdgpu_buffer_rsrc_t r, uint32_t vof
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow, int trow_u, int trow_p) {
-    using Z = TB2;
+// One workgroup's tile and z-chunk (logical block lb of the field set v).
+template <int MODE, int R_, typename T>
+__device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb, int arow, int trow_u, int trow_p,
+                                         float* __restrict__ lds) {
+    constexpr bool WAVE = MODE == MODE_WAVE;
+    using Z = TB2<R_, WAVE>;
     using S = Storage<T>;
     constexpr int R = Z::R, Q = Z::Q, TX = Z::TX, TY = Z::TY, NT = Z::NT;
     constexpr int EG = Z::EG, EY = Z::EY, W1 = Z::W1, P1 = Z::P1, W2 = Z::W2, P2 = Z::P2, NS2 = Z::NS2;
-    extern __shared__ __attribute__((aligned(16))) float lds[];
     float* const U1 = lds;
     float* const U2 = lds + Z::NS1 * P1;
     float4* const BQ = reinterpret_cast<float4*>(U2 + NS2 * P2);
 
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     const int ntxy = v.ntx * v.nty;
     const int tile_x = lb % v.ntx, tile_y = (lb / v.ntx) % v.nty, zch = lb / ntxy;
@@ -230,12 +234,9 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
     const int64_t sz = v.g.s[0], sy = v.g.s[1];
     const T* U = (const T*)v.u + v.g.origin;
     const T* P = (const T*)v.prev + v.g.origin;
-    const T* B = (const T*)v.beta + v.g.origin;
-    T* O1 = (T*)v.out1 + v.g.origin;
-    T* O2 = (T*)v.out2 + v.g.origin;
 
     // receivers sample the two input levels (neither is written here)
-    if (lb == 0 && v.rec.n > 0) {
+    if (WAVE && lb == 0 && v.rec.n > 0) {
         for (int r = tid; r < v.rec.n; r += NT) {
             if (trow_u >= 0) v.rec.trace[(int64_t)trow_u * v.rec.n + r] = (double)S::load(U + v.rec.off[r]);
             if (trow_p >= 0) v.rec.trace[(int64_t)trow_p * v.rec.n + r] = (double)S::load(P + v.rec.off[r]);
@@ -259,7 +260,8 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
     auto rsrc = [&](const void* f) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(f), (short)0, (int)v.range, kBufferConfig);
     };
-    const auto rU = rsrc(v.u), rP = rsrc(v.prev), rB = rsrc(v.beta), rO1 = rsrc(v.out1), rO2 = rsrc(v.out2);
+    const auto rU = rsrc(v.u), rO2 = rsrc(v.out2);
+    const auto rP = WAVE ? rsrc(v.prev) : rU, rB = WAVE ? rsrc(v.beta) : rU, rO1 = WAVE ? rsrc(v.out1) : rO2;
     auto ld = [&](__amdgpu_buffer_rsrc_t r, int z, uint32_t off) -> float4 { return tb2_bload4<T>(r, off, soff(z)); };
 
     // This thread's group of E (ex, ey): tile role (ex, ey) = (gx + 1, gy + R);
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         ex = tid % (TX / 4) + 1;
         ey = tid / (TX / 4) + R;
     } else {
-        tb2_ring_group(min(k, Z::NRING - 1), ex, ey);
+        tb2_ring_group<R>(min(k, Z::NRING - 1), ex, ey);
     }
     const int x0 = X0 - 4 + 4 * ex, y0 = Y0 - R + ey;
     const uint32_t ag = goff(x0, y0);
@@ -315,12 +317,19 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         qa[j] = ld(rU, z1b - R + j, ag);
         qx[j] = tile_role ? make_float4(0.f, 0.f, 0.f, 0.f) : ld(rU, z1b - R + j, am);
     }
-    float4 cp = ld(rP, z1b, ag), cb = ld(rB, z1b, ag);
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 cp = zero4, cb = zero4;
+    if constexpr (WAVE) {
+        cp = ld(rP, z1b, ag);
+        cb = ld(rB, z1b, ag);
+    }
 
-    // sources: stage 1 walks the sources inside E, stage 2 the tile's own
-    int e_next, e_end, e_z, t_next, t_end, t_z;
-    tb2_src_first(v.src_e, tile, z1b, e_next, e_end, e_z);
-    tb2_src_first(v.src_t, tile, zb, t_next, t_end, t_z);
+    // sources (wave): stage 1 walks the sources inside E, stage 2 the tile's own
+    int e_next = 0, e_end = 0, e_z = INT_MAX, t_next = 0, t_end = 0, t_z = INT_MAX;
+    if constexpr (WAVE) {
+        tb2_src_first(v.src_e, tile, z1b, e_next, e_end, e_z);
+        tb2_src_first(v.src_t, tile, zb, t_next, t_end, t_z);
+    }
 
     int it = 0;   // plane counter: u^n LDS slot it & 1
     int s2 = 0;   // LDS slot of u^{n+1} plane z1
@@ -336,17 +345,20 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         auto zb2 = [&](int j) -> float4 { return qx[(j + OFF2) % Q]; };
         float* L1 = U1 + (it & 1) * P1;
         *reinterpret_cast<float4*>(&L1[l1]) = za(R);
-        if (tile_role)
-            BQ[s2 * Z::NTILE + tid] = cb;
-        else
+        if (tile_role) {
+            if constexpr (WAVE) BQ[s2 * Z::NTILE + tid] = cb;
+        } else {
             *reinterpret_cast<float4*>(&L1[lm]) = qx[(R + OFF) % Q];
+        }
 
         const bool more = z1 + 1 < z1e;
         float4 nq, np, nb, nm;
         if (more) {
             nq = ld(rU, z1 + 1 + R, ag);
-            np = ld(rP, z1 + 1, ag);
-            nb = ld(rB, z1 + 1, ag);
+            if constexpr (WAVE) {
+                np = ld(rP, z1 + 1, ag);
+                nb = ld(rB, z1 + 1, ag);
+            }
             if (!tile_role) nm = ld(rU, z1 + 1 + R, am);
         }
         __syncthreads();
@@ -356,8 +368,8 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         {
             const bool zin = z1 >= 0 && z1 < nz;
             float o[4];
-            tb2_star(w, za, L1 + l1, W1, cp, cb, o);
-            while (e_z == z1) {
+            tb2_star<R, MODE>(w, za, L1 + l1, W1, cp, cb, o);
+            while (WAVE && e_z == z1) {
                 const int* e = v.src_e.zyx4 + 4 * e_next;
                 e_next++;
                 e_z = e_next < e_end ? v.src_e.zyx4[4 * e_next] : INT_MAX;
@@ -376,7 +388,7 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         // ---- stage 2 (tile role): u^{n+2} at plane z = z1 - R
         if (tile_role) {
             qx[(2 * R + OFF2) % Q] = r1;
-            if (z1 >= zb && z1 < ze && store_ok) {
+            if (WAVE && z1 >= zb && z1 < ze && store_ok) {
                 const float o[4] = {r1.x, r1.y, r1.z, r1.w};
                 tb2_store<T>(rO1, ag, soff(z1), full_tile, x0, nx, o);
             }
@@ -384,8 +396,11 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
             if (z >= zb) {
                 const int sz2 = s2 + 1 == NS2 ? 0 : s2 + 1;   // slot of plane z1 - R
                 float o2[4];
-                tb2_star(w, zb2, U2 + sz2 * P2 + l2, W2, za(0), BQ[sz2 * Z::NTILE + tid], o2);
-                while (t_z == z) {
+                if constexpr (WAVE)
+                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, za(0), BQ[sz2 * Z::NTILE + tid], o2);
+                else
+                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, zero4, zero4, o2);
+                while (WAVE && t_z == z) {
                     const int* e = v.src_t.zyx4 + 4 * t_next;
                     t_next++;
                     t_z = t_next < t_end ? v.src_t.zyx4[4 * t_next] : INT_MAX;
@@ -401,8 +416,10 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
         if (more) {
             qa[OFF] = nq;
             if (!tile_role) qx[OFF] = nm;
-            cp = np;
-            cb = nb;
+            if constexpr (WAVE) {
+                cp = np;
+                cb = nb;
+            }
         }
         s2 = s2 + 1 == NS2 ? 0 : s2 + 1;
         it++;
@@ -414,15 +431,45 @@ __global__ __launch_bounds__(TB2::NT, 1) void k_tb2(TBView v, Coefs w, int arow,
     });
 }
 
+template <int MODE, int R, typename T>
+__global__ __launch_bounds__(kTB2Threads, (TB2<R, MODE == MODE_WAVE>::WAVES_PER_SIMD)) void k_tb2(TBView v, Coefs w, int arow,
+                                                                                               int trow_u, int trow_p) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    tb2_tile<MODE, R, T>(v, w, xcd_remap(blockIdx.x, gridDim.x), arow, trow_u, trow_p, lds);
+}
+
+// Batched shots: one launch covers the tiles of every shot; block_map[2 lb],
+// block_map[2 lb + 1] = shot and block within the shot of logical block lb.
 template <typename T>
-static hipError_t tb2_launch(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s) {
-    constexpr size_t lds = sizeof(float) * TB2::LDS_FLOATS;
-    const int64_t nb = (int64_t)v.ntx * v.nty * v.nzc;
-    if (nb == 0) return hipSuccess;
-    auto k = k_tb2<T>;
+__global__ __launch_bounds__(kTB2Threads, 1) void k_tb2_batch(const TBView* __restrict__ views,
+                                                         const int* __restrict__ block_map, Coefs w, int arow,
+                                                         int trow_u, int trow_p) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    tb2_tile<MODE_WAVE, 4, T>(views[block_map[2 * lb]], w, block_map[2 * lb + 1], arow, trow_u, trow_p, lds);
+}
+
+template <typename T>
+static hipError_t tb2_batch_launch(const TBView* views, const int* bmap, int nblocks, const Coefs& w, int arow,
+                                   int trow_u, int trow_p, hipStream_t s) {
+    constexpr size_t lds = sizeof(float) * TB2<4, true>::LDS_FLOATS;
+    if (nblocks == 0) return hipSuccess;
+    auto k = k_tb2_batch<T>;
     static const hipError_t attr = allow_lds(k, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(TB2::NT), lds, s, v, w, arow, trow_u, trow_p);
+    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kTB2Threads), lds, s, views, bmap, w, arow, trow_u, trow_p);
+    return hipGetLastError();
+}
+
+template <int MODE, int R, typename T>
+static hipError_t tb2_launch(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s) {
+    constexpr size_t lds = sizeof(float) * TB2<R, MODE == MODE_WAVE>::LDS_FLOATS;
+    const int64_t nb = (int64_t)v.ntx * v.nty * v.nzc;
+    if (nb == 0) return hipSuccess;
+    auto k = k_tb2<MODE, R, T>;
+    static const hipError_t attr = allow_lds(k, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(kTB2Threads), lds, s, v, w, arow, trow_u, trow_p);
     return hipGetLastError();
 }
 

@@ -191,6 +191,8 @@ def test_batch_plan_validation():
         S.BatchPlan([(10, 10, 10)], 2, S.second_derivative_weights(4))
     bp = S.BatchPlan([(10, 12, 14), (20, 9, 33)], 4, S.second_derivative_weights(8))
     assert len(bp.layouts) == 2
+    assert bp.variant_count() == 20
+    assert bp.variant_name(17).startswith("tb2_")
     assert list(bp.layouts[1].extents) == [28, 17, 41]
     with pytest.raises(S.StencilError):
         bp.variant = 0

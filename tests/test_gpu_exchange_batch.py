@@ -97,11 +97,15 @@ def test_decomposed_equals_monolithic_on_gpu(device, parts, periodic):
     assert np.array_equal(out, ma)
 
 
-def test_batched_equals_sequential_bitwise(device):
+@pytest.mark.parametrize("steps", [17, 14])
+def test_batched_equals_sequential_bitwise(device, steps):
+    # plain batched variants and the temporally blocked ones (tb2_*: two-step
+    # passes over all shots, plain batched sweeps for the remaining steps)
     import torch
-    shapes = [(20, 33, 45), (37, 16, 70), (28, 28, 28), (9, 40, 12)]
-    steps = 17
+    shapes = [(20, 33, 45), (37, 16, 70), (28, 28, 28), (9, 40, 12), (40, 70, 130)]
     bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
+    tb = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("tb2_")]
+    assert len(tb) == 3
     fields, srcs, amps, recs, trs, ins = [], [], [], [], [], []
     for i, sh in enumerate(shapes):
         u0, um1, beta = wave_inputs(sh, seed=100 + i)
@@ -114,7 +118,7 @@ def test_batched_equals_sequential_bitwise(device):
         amps.append(torch_f64(np.random.default_rng(200 + i).standard_normal((steps, 1)), device))
         recs.append(np.array([[1, 2, 3], [s - 1 for s in sh]][: 1 + i % 2]))
         trs.append(torch.zeros((steps, len(recs[-1])), dtype=torch.float64, device=device))
-    for v in (1, 5, 9):
+    for v in (1, 5, 9, *tb):
         bp.variant = v
         for i in range(len(shapes)):
             for fld, a in zip(fields[i], ins[i]):
