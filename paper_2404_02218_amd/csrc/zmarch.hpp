@@ -310,11 +310,21 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     for (int i = 0; i < VX; i++)
                         if (x0 + i < nx) S::store(O + off + i, o[j][i]);
                 }
+                // D (written by the recompute, read once by the adjoint many
+                // steps later) and the imaging partial G (read and written once
+                // per step) stream past the caches
                 if constexpr (MODE == MODE_WAVE_D) {
                     float* D = v.dfield + v.g.origin + off;
+                    if (full) {
 #pragma unroll
-                    for (int i = 0; i < VX; i++)
-                        if (x0 + i < nx) D[i] = dv[j][i];
+                        for (int c = 0; c < NV; c++)
+                            Storage<float>::store4_nt(D + 4 * c, make_float4(dv[j][4 * c], dv[j][4 * c + 1],
+                                                                             dv[j][4 * c + 2], dv[j][4 * c + 3]));
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < VX; i++)
+                            if (x0 + i < nx) D[i] = dv[j][i];
+                    }
                 }
                 if constexpr (MODE == MODE_WAVE_ADJ) {
                     const float* D = v.dfield + v.g.origin + off;
@@ -322,13 +332,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     if (full) {
 #pragma unroll
                         for (int c = 0; c < NV; c++) {
-                            const float4 d = *reinterpret_cast<const float4*>(D + 4 * c);
-                            float4 g = *reinterpret_cast<const float4*>(G + 4 * c);
+                            const float4 d = Storage<float>::load4_nt(D + 4 * c);
+                            float4 g = Storage<float>::load4_nt(G + 4 * c);
                             g.x = fmaf(o[j][4 * c], d.x, g.x);
                             g.y = fmaf(o[j][4 * c + 1], d.y, g.y);
                             g.z = fmaf(o[j][4 * c + 2], d.z, g.z);
                             g.w = fmaf(o[j][4 * c + 3], d.w, g.w);
-                            *reinterpret_cast<float4*>(G + 4 * c) = g;
+                            Storage<float>::store4_nt(G + 4 * c, g);
                         }
                     } else {
 #pragma unroll
