@@ -227,6 +227,7 @@ struct stencil_plan_s {
     std::vector<PointTables> shot_src, shot_rec;
     DevTable views, block_map;   // block_map: (shot, block within the shot) per workgroup
     std::vector<int> bstart;
+    int nblocks = 0;             // workgroups of a batched launch (with padding)
     // batched temporal blocking: per-shot extended source lists, the second
     // field pair of every shot, and the view tables of even and odd passes
     std::vector<PointTables> shot_src_ext;
@@ -928,14 +929,51 @@ stencil_status stencil_batch_layout(stencil_plan p, int shot, int64_t* extents, 
     return layout_out(p->shots[shot], extents, strides, offset, bytes);
 }
 
-// (shot, block within the shot) for every workgroup of a batched launch,
-// from the prefix sum of the shots' workgroup counts
-static stencil_status upload_block_map(const std::vector<int>& bstart, DevTable& table) {
-    std::vector<int> map(2 * (size_t)std::max(1, bstart.back()), 0);
-    for (size_t sh = 0; sh + 1 < bstart.size(); sh++)
-        for (int b = bstart[sh]; b < bstart[sh + 1]; b++) {
-            map[2 * (size_t)b] = (int)sh;
-            map[2 * (size_t)b + 1] = b - bstart[sh];
+// Block map of a batched launch: (shot, block within the shot) per
+// workgroup, or shot -1 for a padding workgroup that exits at once.  The
+// hardware hands workgroup b to XCD b % 8 and each XCD runs its workgroups in
+// order, so the map is laid out per XCD: every (shot, z-chunk) group of tiles
+// (neighbours that share halo rows, kept on one XCD for its L2) goes to the
+// XCD with the least work so far, largest groups first, and each XCD's list
+// is padded to the longest.  Work of a group = tiles x (chunk planes + 2r).
+static stencil_status build_block_map_impl(const std::vector<ZView>& views, const std::vector<int>& nz, int radius,
+                                           DevTable& table, int& nblocks) {
+    constexpr int kXcds = 8;
+    struct Group {
+        int shot, chunk, tiles;
+        int64_t work;
+    };
+    std::vector<Group> groups;
+    for (size_t sh = 0; sh < views.size(); sh++) {
+        const ZView& v = views[sh];
+        const int tiles = v.ntx * v.nty;
+        for (int c = 0; c < v.nzc; c++) {
+            const int len = std::min(v.zc, nz[sh] - c * v.zc);
+            groups.push_back({(int)sh, c, tiles, (int64_t)tiles * (len + 2 * radius)});
+        }
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.work > b.work; });
+    std::vector<std::vector<int>> lists(kXcds);
+    std::vector<int64_t> load(kXcds, 0);
+    for (const Group& g : groups) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += g.work;
+        const int ntxy = g.tiles;
+        for (int t = 0; t < ntxy; t++) {
+            lists[x].push_back(g.shot);
+            lists[x].push_back(g.chunk * ntxy + t);
+        }
+    }
+    size_t len = 0;
+    for (const auto& l : lists) len = std::max(len, l.size() / 2);
+    if (len * kXcds > (size_t(1) << 30)) return fail(STENCIL_E_INVALID, "batch too large");
+    nblocks = (int)(len * kXcds);
+    std::vector<int> map(2 * std::max<size_t>(1, len * kXcds), -1);
+    for (int x = 0; x < kXcds; x++)
+        for (size_t i = 0; i < lists[x].size() / 2; i++) {
+            const size_t b = i * kXcds + x;
+            map[2 * b] = lists[x][2 * i];
+            map[2 * b + 1] = lists[x][2 * i + 1];
         }
     return table.upload(map.data(), sizeof(int) * map.size());
 }
@@ -967,7 +1005,11 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
     }
     (void)nsteps;
     ST_TRY(p->views.upload(views.data(), sizeof(ZView) * views.size()));
-    ST_TRY(upload_block_map(p->bstart, p->block_map));
+    {
+        std::vector<int> nz(ns);
+        for (int s = 0; s < ns; s++) nz[s] = p->shots[s].g.n[0];
+        ST_TRY(build_block_map_impl(views, nz, p->radius, p->block_map, p->nblocks));
+    }
     if (var.tb) {
         // pass k reads pair k & 1 (newest, previous) and writes the other pair
         // (u^{n+2} into its first buffer, u^{n+1} into its second)
@@ -1010,7 +1052,7 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
 static stencil_status enqueue_batch(stencil_plan p, const std::vector<ZView>& views, int64_t nsteps, const Variant& var,
                                     bool any_rec, hipStream_t s) {
     const int ns = (int)p->shots.size();
-    const int nblocks = p->bstart[ns];
+    const int nblocks = p->nblocks;
     int64_t t0 = 0;
     if (var.tb) {
         // an even number of two-step passes (as in a single-plan run), then
@@ -1412,7 +1454,13 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
         }
         if (p->batch) {
             st = vt.upload(views.data(), sizeof(ZView) * views.size());
-            if (st == STENCIL_OK) st = upload_block_map(bst, bs);
+            int padded = 0;
+            if (st == STENCIL_OK) {
+                std::vector<int> nz;
+                for (const Layout* L : Ls) nz.push_back(L->g.n[0]);
+                st = build_block_map_impl(views, nz, p->radius, bs, padded);
+            }
+            bst.back() = padded;
             if (st == STENCIL_OK && var.tb) {
                 std::vector<TBView> tv;
                 int64_t o2 = off;

@@ -378,16 +378,17 @@ __global__ __launch_bounds__(BX* BY) void k_zmarch(ZView v, Coefs w, int parity,
     zmarch_tile<MODE, R, T, BX, BY, VY, VX, NTH>(v, w, lb, parity, arow, trow, lds);
 }
 
-// Batched shots: block_map[2 lb], block_map[2 lb + 1] = shot and block within
-// the shot of logical block lb (one load instead of a search over the
-// shots' block counts, whose dependent loads would delay every workgroup).
+// Batched shots: block_map[2 b], block_map[2 b + 1] = shot and block within
+// the shot of workgroup b; shot -1 pads the map (the host lays it out per
+// XCD, so it replaces xcd_remap here).
 template <int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict__ views,
                                                         const int* __restrict__ block_map, Coefs w, int parity,
                                                         int arow, int trow) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int shot = block_map[2 * lb], local = block_map[2 * lb + 1];
+    const int b = blockIdx.x;
+    const int shot = block_map[2 * b], local = block_map[2 * b + 1];
+    if (shot < 0) return;
     const ZView v = views[shot];
     zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, local, parity, arow, trow, lds);
 }

@@ -438,15 +438,17 @@ __global__ __launch_bounds__(kTB2Threads, (TB2<R, MODE == MODE_WAVE>::WAVES_PER_
     tb2_tile<MODE, R, T>(v, w, xcd_remap(blockIdx.x, gridDim.x), arow, trow_u, trow_p, lds);
 }
 
-// Batched shots: one launch covers the tiles of every shot; block_map[2 lb],
-// block_map[2 lb + 1] = shot and block within the shot of logical block lb.
+// Batched shots: one launch covers the tiles of every shot; block_map as for
+// k_zmarch_batch (laid out per XCD by the host; shot -1 pads).
 template <typename T>
 __global__ __launch_bounds__(kTB2Threads, 1) void k_tb2_batch(const TBView* __restrict__ views,
                                                          const int* __restrict__ block_map, Coefs w, int arow,
                                                          int trow_u, int trow_p) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    tb2_tile<MODE_WAVE, 4, T>(views[block_map[2 * lb]], w, block_map[2 * lb + 1], arow, trow_u, trow_p, lds);
+    const int b = blockIdx.x;
+    const int shot = block_map[2 * b];
+    if (shot < 0) return;
+    tb2_tile<MODE_WAVE, 4, T>(views[shot], w, block_map[2 * b + 1], arow, trow_u, trow_p, lds);
 }
 
 template <typename T>
