@@ -37,10 +37,9 @@ METRIC = "GPts/s + % of HBM peak, 3D so-8 wave; batched & adjoint vs plain, same
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 # the counters are tied to every source of the library (kernels and the
 # runtime that picks their launch shapes)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_02218_amd", "csrc", f)
-                  for f in ("device.hpp", "kernels.hpp", "zmarch.hpp", "zmarch_tb.hpp", "zmarch_tb.hip",
-                            "zmarch_f32.hip", "zmarch_adj.hip", "zmarch_bf16.hip", "zmarch_f16.hip",
-                            "kernels.hip", "runtime.cpp")]
+CSRC = os.path.join(ROOT, "paper_2404_02218_amd", "csrc")
+KERNEL_SOURCES = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                        if f.endswith((".hip", ".hpp", ".cpp", ".h")))
 
 
 def log(*a):
@@ -55,6 +54,9 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="interior edge of the headline workload")
     ap.add_argument("--nsteps", type=int, default=400, help="leapfrog steps per bench step")
     ap.add_argument("--only-main", action="store_true", help="headline workload only (profiling)")
+    ap.add_argument("--only-heat", action="store_true",
+                    help="the 3D so-4 heat leg only, --variant and --heat-steps apply (profiling)")
+    ap.add_argument("--heat-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -163,7 +165,7 @@ def time_wave(plan, f, amp, P, steps, warmup):
     return t.ms / steps
 
 
-def cpu_baseline(W, n, budget_s=12.0):
+def cpu_baseline(W, n, budget_s=20.0):
     """FP64 oracle on the host cores: the headline recipe at its own n^3
     interior, as many leapfrog steps as fit in about budget_s seconds."""
     import oracle
@@ -243,6 +245,34 @@ def bench_batch(S, W, steps):
             "bitwise_equal_to_sequential": bool(same),
             "variant": bp.variant_name(bp.variant),
             "sequential_variants": sorted({p.variant_name(p.variant) for p, _ in plans})}
+
+
+def bench_heat3d(S, W, steps, variant=-1, nsteps=50):
+    """3D 13-point heat (so-4), 512^3, alpha = 0.05, Dirichlet zero halo of 2."""
+    H = W.heat3d_c2(nsteps=nsteps)
+    hp = S.Plan(S.HEAT, H.shape, 2, S.heat_weights(4, H.alpha), halo=2)
+    hf = [hp.field() for _ in range(2)]
+    hf[0].load(W.embed(W.round_to_storage(H.u0, "f32"), 2))
+    if variant >= 0:
+        hp.variant = variant
+    else:
+        hp.tune(hf, reps=3)
+    hp.run(hf, H.nsteps)
+    with Timer() as t:
+        for _ in range(steps):
+            hp.run(hf, H.nsteps)
+    hms = t.ms / steps
+    npts = float(np.prod(H.shape))
+    hg = npts * H.nsteps / (hms * 1e-3) / 1e9
+    hvn = hp.variant_name(hp.variant)
+    # launches: a tb2 pass reads u^n and writes u^{n+2} (8 B per point for
+    # two steps); a plain sweep moves 8 B per point for one step
+    _, hl, _, _ = launch_model(hvn, H.nsteps, 4, "f32")
+    halg = 8.0 * npts * hl / (hms * 1e-3) / 1e9
+    log(f"[bench] heat {hvn}: {hms:.3f} ms per run, {hg:.1f} GPts/s, {halg:.0f} GB/s algorithmic")
+    return {"GPts_s": round(hg, 2), "ms_per_run": round(hms, 3), "steps": H.nsteps, "variant": hvn,
+            "launches_per_run": hl, "algorithmic_GBps": round(halg, 1), "frac_hbm": round(halg / HBM_PEAK_GBS, 4),
+            "effective_GBps_plain_sweep_bytes": round(hg * 8, 1)}
 
 
 def bench_heat2d(S, W, steps):
@@ -434,6 +464,12 @@ def main():
         sys.exit(1)
     n, nsteps = args.n, args.nsteps
     pts = float(n) ** 3 * nsteps
+    if args.only_heat:
+        out = {"heat3d_so4": bench_heat3d(S, W, args.steps, args.variant, args.heat_steps)}
+        if args.copy_calibration:
+            out["stream_copy_GBps"] = round(stream_copy_gbs(), 1)
+        print(json.dumps(out), flush=True)
+        return
 
     log(f"[bench] headline: so-8 wave {n}^3 x {nsteps} steps, {args.storage} storage")
     P, plan, f, amp = wave_setup(S, W, n, nsteps, S.DTYPES[args.storage], args.variant)
@@ -491,28 +527,7 @@ def main():
             del f2
             torch.cuda.empty_cache()
         log("[bench] heat so-4 512^3 x 50")
-        H = W.heat3d_c2()
-        hp = S.Plan(S.HEAT, H.shape, 2, S.heat_weights(4, H.alpha), halo=2)
-        hf = [hp.field() for _ in range(2)]
-        hf[0].load(W.embed(W.round_to_storage(H.u0, "f32"), 2))
-        hp.tune(hf, reps=3)
-        hp.run(hf, H.nsteps)
-        with Timer() as t:
-            for _ in range(3):
-                hp.run(hf, H.nsteps)
-        hms = t.ms / 3
-        npts = float(np.prod(H.shape))
-        hg = npts * H.nsteps / (hms * 1e-3) / 1e9
-        hvn = hp.variant_name(hp.variant)
-        # launches: a tb2 pass reads u^n and writes u^{n+2} (8 B per point for
-        # two steps); a plain sweep moves 8 B per point for one step
-        _, hl, _, _ = launch_model(hvn, H.nsteps, 4, "f32")
-        halg = 8.0 * npts * hl / (hms * 1e-3) / 1e9
-        extras["heat3d_so4"] = {"GPts_s": round(hg, 2), "ms_per_run": round(hms, 3), "variant": hvn,
-                                "launches_per_run": hl, "algorithmic_GBps": round(halg, 1),
-                                "frac_hbm": round(halg / HBM_PEAK_GBS, 4),
-                                "effective_GBps_plain_sweep_bytes": round(hg * 8, 1)}
-        del hf
+        extras["heat3d_so4"] = bench_heat3d(S, W, 3, args.variant)
         torch.cuda.empty_cache()
         log("[bench] heat 2D 256^2 x 100")
         extras["heat2d_so2"] = bench_heat2d(S, W, 20)
