@@ -275,6 +275,33 @@ def bench_heat3d(S, W, steps, variant=-1, nsteps=50):
             "effective_GBps_plain_sweep_bytes": round(hg * 8, 1)}
 
 
+def bench_pw(S, W, steps, n=512):
+    """The flux-form C-grid advection of (u, v, w) as a 60-term stencil
+    program (3 inputs, 3 outputs, diagonal offsets), 512^3 interior (the
+    134M-point size of the paper's PW advection runs), random velocity,
+    zero halo.  One program apply per step."""
+    import torch
+    from paper_2404_02218_amd.program import Program, pw_advection_terms
+    shape = (n, n, n)
+    prog = Program(shape, 1, 3, 3, pw_advection_terms(1.0, 1.0, 1.0))
+    gen = torch.Generator(device="cuda").manual_seed(W.SEED_BASE + 6)
+    ins = [prog.field() for _ in range(3)]
+    for f in ins:
+        f.view[1:-1, 1:-1, 1:-1] = torch.rand(shape, generator=gen, device="cuda") - 0.5
+    outs = [prog.field() for _ in range(3)]
+    prog.apply_program(outs, ins)
+    with Timer() as t:
+        for _ in range(steps):
+            prog.apply_program(outs, ins)
+    ms = t.ms / steps
+    pts = float(n) ** 3
+    gbs = 24.0 * pts / (ms * 1e-3) / 1e9
+    log(f"[bench] pw advection {n}^3: {ms:.3f} ms, {pts / (ms * 1e-3) / 1e9:.1f} GPts/s")
+    return {"interior": list(shape), "terms": len(prog.terms), "GPts_s": round(pts / (ms * 1e-3) / 1e9, 2),
+            "ms_per_apply": round(ms, 3), "algorithmic_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_point": 24, "kernel": "k_program (60 terms read from LDS)"}
+
+
 def bench_heat2d(S, W, steps):
     """2D 5-point heat, 256^2, Dirichlet zero halo, 100 steps: a field of
     260 KiB stays in L2, so this measures launch and synchronisation cost
@@ -536,6 +563,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] face pack/unpack")
         extras["halo_faces"] = bench_faces(S, W)
+        torch.cuda.empty_cache()
+        log("[bench] pw advection program")
+        extras["pw_advection_program"] = bench_pw(S, W, 10)
         torch.cuda.empty_cache()
         if not args.no_batch:
             log("[bench] batched shots")

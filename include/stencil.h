@@ -147,6 +147,19 @@ stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, con
 stencil_status stencil_exchanges(stencil_plan plan, const int32_t* grid, const int32_t* coord,
                                  int periodic, stencil_exchange* out, int* n);
 
+/* Exchange declarations including edges and corners: one per neighbour
+ * direction d in {-1, 0, 1}^ndim other than 0 (3^ndim - 1 in all; 26 in 3D),
+ * in C order of d with -1 before 0 before +1.  Per axis, d = -1 receives
+ * [h - r, h) from the neighbour below (send box shifted by +r), d = +1
+ * receives [h + n, h + n + r) (send box shifted by -r), d = 0 spans the
+ * interior.  Needed by stencils that read diagonal offsets (a stencil
+ * program's terms can; Section 4.2 declares exchanges as boxes, so an edge or
+ * corner is one more box).  A direction exists when every axis with d != 0
+ * has that neighbour, or `periodic`.  For a program plan r is its largest
+ * offset.  *n: in = capacity of `out`, out = count. */
+stencil_status stencil_exchanges_box(stencil_plan plan, const int32_t* grid, const int32_t* coord,
+                                     int periodic, stencil_exchange* out, int* n);
+
 /* Pack the send boxes of n exchanges (host array) from `field` into `buf`
  * (device), each box in C order, concatenated in declaration order.  The
  * number of elements is the sum of the box volumes; buf has the field's
@@ -212,6 +225,43 @@ stencil_status stencil_adjoint(stencil_plan plan, const void* beta, int64_t nste
  * dense interior FP64 array m (device), rounded to the plan's dtype. */
 stencil_status stencil_wave_beta(stencil_plan plan, const double* m, double dt, double h, void* beta,
                                  void* stream);
+
+/* ------------------------------------------------------- stencil programs */
+
+/* One term of a stencil program.  A program computes nout output fields
+ * from nin input fields at every interior point i: output o is the sum, in
+ * program order, of its terms coeff * in[a](i + off_a), or
+ * coeff * in[a](i + off_a) * in[b](i + off_b) for two factors (several
+ * stencil.apply computations over several fields fused into one region, as
+ * Section 6.2 describes for PW advection; the accesses are stencil.access at
+ * relative offsets, Section 4.1).  Offsets are in C order (z, y, x); for
+ * ndim < 3 the leading entries are 0. */
+typedef struct {
+    int32_t out;       /* output field, 0 .. nout-1 */
+    int32_t nfac;      /* 1 or 2 */
+    int32_t in[2];     /* input field of each factor, 0 .. nin-1 */
+    int32_t off[2][3]; /* offset of each factor */
+    double coeff;      /* rounded to FP32 for the device */
+} stencil_term;
+
+/* A program plan over interior `shape` (ndim 1..3) with halo `halo`: nin in
+ * [1, 4] input and nout in [1, 4] output fields of FP32 storage sharing the
+ * plan's layout (stencil_layout), nterms in [1, 64] terms (copied).  Every
+ * offset must lie within min(halo, 2).  Errors: STENCIL_E_INVALID for bad
+ * indices or offsets, STENCIL_E_UNSUPPORTED for other dtypes or sizes beyond
+ * these limits.  stencil_layout, stencil_exchanges(_box), stencil_halo_pack
+ * and _unpack and stencil_destroy accept the plan. */
+stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t* shape, int halo, int nin,
+                                      int nout, const stencil_term* terms, int nterms, stencil_dtype dtype);
+
+/* Evaluate the program once: outs[nout] and ins[nin] are device field
+ * pointers (256-byte aligned).  Interior points of every output are
+ * written; halos are read from the inputs as they are (refresh them with an
+ * exchange first where needed) and outputs' halos are untouched.  No output
+ * may alias an input or another output.  Each term evaluates as
+ * fl(fl(coeff * a) * b), added to its output's FP32 sum in program order
+ * (no fused multiply-add). */
+stencil_status stencil_program_apply(stencil_plan plan, void* const* outs, const void* const* ins, void* stream);
 
 /* ------------------------------------------------------------ variants */
 

@@ -1,6 +1,7 @@
 """FP64 CPU oracle for the star-stencil sweep: heat/Jacobi, second-order
-acoustic wave, its adjoint and misfit gradient, and the halo exchange
-declarations with pack/unpack.
+acoustic wave, its adjoint and misfit gradient, the halo exchange
+declarations (faces, or faces, edges and corners) with pack/unpack, fused
+stencil programs over several fields, and a flux-form C-grid advection.
 
 TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package.  It shares no code with the GPU
@@ -57,6 +58,9 @@ def _load():
     lib.orc_wave_gradient.argtypes = [C.c_int, P, C.c_int, C.c_int, P, P, I64, I64, P, P, I64,
                                       P, P, P, C.c_double, P, P, P]
     lib.orc_exchanges.argtypes = [C.c_int, P, C.c_int, C.c_int, P, P, C.c_int, P, P]
+    lib.orc_exchanges_box.argtypes = [C.c_int, P, C.c_int, C.c_int, P, P, C.c_int, P, P]
+    lib.orc_program.argtypes = [C.c_int, P, C.c_int, C.c_int, P, C.c_int, P, C.c_int, P]
+    lib.orc_pw_advection.argtypes = [P, C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P]
     lib.orc_pack.argtypes = [C.c_int, P, C.c_int, P, P, C.c_int, P]
     lib.orc_unpack.argtypes = [C.c_int, P, C.c_int, P, P, C.c_int, P]
     for f in ("orc_star", "orc_heat_run", "orc_wave_run", "orc_wave_adjoint",
@@ -176,18 +180,65 @@ def wave_gradient(beta, halo, radius, c, nsteps, src, src_amp, rec, dobs, rec_w,
     return traces, float(J[0]), grad
 
 
-def exchanges(shape, halo, radius, grid, coord, periodic=False):
-    """Exchange declarations of one rank (list of Exchange)."""
+def exchanges(shape, halo, radius, grid, coord, periodic=False, box=False):
+    """Exchange declarations of one rank (list of Exchange): faces only, or
+    with box=True faces, edges and corners (every neighbour direction)."""
     lib = _load()
     ndim = len(shape)
     shp = np.asarray(shape, dtype=np.int64)
     g = np.asarray(grid, dtype=np.int32)
     cc = np.asarray(coord, dtype=np.int32)
-    arr = (Exchange * 6)()
-    n = C.c_int(6)
-    _check(lib.orc_exchanges(ndim, _p(shp), halo, radius, _p(g), _p(cc), int(periodic),
-                             C.cast(arr, C.c_void_p), C.byref(n)), "exchanges")
+    arr = (Exchange * 26)()
+    n = C.c_int(26)
+    fn = lib.orc_exchanges_box if box else lib.orc_exchanges
+    _check(fn(ndim, _p(shp), halo, radius, _p(g), _p(cc), int(periodic), C.cast(arr, C.c_void_p), C.byref(n)),
+           "exchanges")
     return [arr[i] for i in range(n.value)]
+
+
+class Term(C.Structure):
+    """One program term: out += coeff * in[0](i + off[0]) (* in[1](i + off[1]))."""
+    _fields_ = [("out", C.c_int32), ("nfac", C.c_int32), ("inp", C.c_int32 * 2),
+                ("off", (C.c_int32 * 3) * 2), ("coeff", C.c_double)]
+
+
+def program(ins, halo, nout, terms):
+    """Evaluate a stencil program.  ins: equal-shape FP64 buffers (halo
+    included); terms: (out, coeff, [(field, offset), ...]) with 1 or 2
+    factors and offsets of len(shape) components.  Returns nout buffers with
+    the interior computed and a zero halo."""
+    lib = _load()
+    ins = [_f64(a) for a in ins]
+    ndim = ins[0].ndim
+    shape = _shape_of(ins[0], halo)
+    outs = [np.zeros_like(ins[0]) for _ in range(nout)]
+    arr = (Term * max(1, len(terms)))()
+    for t, (o, c, facs) in enumerate(terms):
+        arr[t].out = o
+        arr[t].coeff = c
+        arr[t].nfac = len(facs)
+        for k, (f, off) in enumerate(facs):
+            arr[t].inp[k] = f
+            off3 = [0] * (3 - ndim) + list(off)
+            for a in range(3):
+                arr[t].off[k][a] = int(off3[a])
+    pin = (C.c_void_p * len(ins))(*[a.ctypes.data for a in ins])
+    pout = (C.c_void_p * nout)(*[a.ctypes.data for a in outs])
+    _check(lib.orc_program(ndim, _p(shape), halo, len(ins), C.cast(pin, C.c_void_p), nout,
+                           C.cast(pout, C.c_void_p), len(terms), C.cast(arr, C.c_void_p)), "program")
+    return outs
+
+
+def pw_advection(u, v, w, halo, dx, dy, dz):
+    """Advective tendencies (su, sv, sw) of a C-grid velocity (3D buffers with
+    their halos already filled); interior computed, halo zero."""
+    lib = _load()
+    u, v, w = _f64(u), _f64(v), _f64(w)
+    shape = _shape_of(u, halo)
+    su, sv, sw = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+    _check(lib.orc_pw_advection(_p(shape), halo, _p(u), _p(v), _p(w), float(dx), float(dy), float(dz),
+                                _p(su), _p(sv), _p(sw)), "pw_advection")
+    return su, sv, sw
 
 
 def _ex_array(ex):

@@ -25,7 +25,19 @@
  *
  *   Halo exchange declarations (the dmp.exchange attribute, Section 4.2): a
  *   receive box [at, at+size), a send box shifted by the source offset and the
- *   relative rank it goes to.  Faces only; corners are never exchanged.
+ *   relative rank it goes to.  Faces only for the star; the box form adds the
+ *   edges and corners a stencil with diagonal offsets reads.
+ *
+ *   A stencil program (several stencil.apply results over several fields,
+ *   fused into one region as Section 6.2 describes for PW advection): each
+ *   output is a sum, in program order, of terms c * f(i + o) or
+ *   c * f(i + o) * g(i + o') over input fields f, g at arbitrary offsets
+ *   within the halo.
+ *
+ *   A Piacsek-Williams-style advection (Section 6.2 names the scheme; no
+ *   formulas are printed): the flux-form, centred advection of the velocity
+ *   (u, v, w) on a staggered C grid, written out directly in
+ *   orc_pw_advection below.
  */
 #include <math.h>
 #include <stdint.h>
@@ -478,6 +490,173 @@ int orc_wave_gradient(int ndim, const int64_t* shape, int halo, int radius, cons
     free(states);
     free(resid);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* box exchanges: faces, edges and corners                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Every neighbour direction d in {-1, 0, 1}^ndim other than 0, in C order
+ * (the first axis slowest, -1 before 0 before +1).  Per axis: d = -1 gives
+ * at = h - r, size r, offset +r; d = 0 the interior [h, h + n) and offset 0;
+ * d = +1 at = h + n, size r, offset -r.  A direction exists when every axis
+ * with d != 0 has that neighbour (or the grid is periodic). */
+int orc_exchanges_box(int ndim, const int64_t* shape, int halo, int radius, const int32_t* grid,
+                      const int32_t* coord, int periodic, orc_exchange* out, int* count) {
+    og g;
+    if (og_init(&g, ndim, shape, halo) || check_common(&g, radius) || !count) return ORC_EINVAL;
+    for (int i = 0; i < ndim; i++)
+        if (grid[i] < 1 || coord[i] < 0 || coord[i] >= grid[i]) return ORC_EINVAL;
+    int cap = *count, k = 0;
+    int ndir = 1;
+    for (int i = 0; i < ndim; i++) ndir *= 3;
+    for (int code = 0; code < ndir; code++) {
+        int d[3] = {0, 0, 0}, rem = code, zero = 1, has = 1;
+        for (int i = ndim - 1; i >= 0; i--) {
+            d[i] = rem % 3 - 1;
+            rem /= 3;
+        }
+        for (int i = 0; i < ndim; i++) {
+            if (d[i] != 0) zero = 0;
+            if (d[i] < 0 && !periodic && coord[i] == 0) has = 0;
+            if (d[i] > 0 && !periodic && coord[i] == grid[i] - 1) has = 0;
+        }
+        if (zero || !has) continue;
+        if (k < cap && out) {
+            orc_exchange* x = &out[k];
+            memset(x, 0, sizeof(*x));
+            for (int i = 0; i < ndim; i++) {
+                if (d[i] < 0) {
+                    x->at[i] = halo - radius;
+                    x->size[i] = radius;
+                    x->src_offset[i] = radius;
+                } else if (d[i] > 0) {
+                    x->at[i] = halo + shape[i];
+                    x->size[i] = radius;
+                    x->src_offset[i] = -radius;
+                } else {
+                    x->at[i] = halo;
+                    x->size[i] = shape[i];
+                }
+                x->to[i] = d[i];
+            }
+        }
+        k++;
+    }
+    *count = k;
+    return (out && k > cap) ? ORC_EINVAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* stencil programs                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* must match the layout the Python wrapper declares */
+typedef struct {
+    int32_t out;
+    int32_t nfac;      /* 1 or 2 */
+    int32_t in[2];
+    int32_t off[2][3]; /* offsets per internal axis (z, y, x) */
+    double coeff;
+} orc_term;
+
+/* out[o] on the interior: the terms of output o summed in program order,
+ * each term coeff * in[a](i + off_a) (* in[b](i + off_b)).  Halos of the
+ * outputs are left as they are. */
+int orc_program(int ndim, const int64_t* shape, int halo, int nin, const double* const* ins, int nout,
+                double* const* outs, int nterms, const orc_term* terms) {
+    og g;
+    if (og_init(&g, ndim, shape, halo) || nin < 1 || nout < 1 || nterms < 0) return ORC_EINVAL;
+    for (int t = 0; t < nterms; t++) {
+        const orc_term* T = &terms[t];
+        if (T->out < 0 || T->out >= nout || T->nfac < 1 || T->nfac > 2) return ORC_EINVAL;
+        for (int f = 0; f < T->nfac; f++) {
+            if (T->in[f] < 0 || T->in[f] >= nin) return ORC_EINVAL;
+            for (int a = 0; a < 3; a++) {
+                int o = T->off[f][a];
+                if (!og_active(&g, a) && o != 0) return ORC_EINVAL;
+                if (o < -halo || o > halo) return ORC_EINVAL;
+            }
+        }
+    }
+    const int64_t lo0 = og_lo(&g, 0), lo1 = og_lo(&g, 1), lo2 = og_lo(&g, 2);
+#pragma omp parallel for schedule(static)
+    for (int64_t z = lo0; z < lo0 + g.n[0]; z++)
+        for (int64_t y = lo1; y < lo1 + g.n[1]; y++)
+            for (int64_t x = lo2; x < lo2 + g.n[2]; x++) {
+                const int64_t p = z * g.s[0] + y * g.s[1] + x;
+                for (int o = 0; o < nout; o++) {
+                    double acc = 0.0;
+                    for (int t = 0; t < nterms; t++) {
+                        const orc_term* T = &terms[t];
+                        if (T->out != o) continue;
+                        double v = T->coeff;
+                        for (int f = 0; f < T->nfac; f++) {
+                            const int64_t q = p + T->off[f][0] * g.s[0] + T->off[f][1] * g.s[1] + T->off[f][2];
+                            v *= ins[T->in[f]][q];
+                        }
+                        acc += v;
+                    }
+                    outs[o][p] = acc;
+                }
+            }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* flux-form centred advection on a C grid                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Velocity on a staggered (Arakawa C) grid: u[k][j][i] lives at the x face
+ * (i + 1/2, j, k), v[k][j][i] at (i, j + 1/2, k), w[k][j][i] at
+ * (i, j, k + 1/2).  The advective tendency of each component is minus the
+ * divergence of its momentum flux, with every product formed from two-point
+ * averages onto the flux position:
+ *   su = -[ dx( (u^x)^2 ) + dy( v^x u^y ) + dz( w^x u^z ) ]
+ *   sv = -[ dx( u^y v^x ) + dy( (v^y)^2 ) + dz( w^y v^z ) ]
+ *   sw = -[ dx( u^z w^x ) + dy( v^z w^y ) + dz( (w^z)^2 ) ]
+ * where q^a is the average of q with its neighbour along a (towards + for
+ * the flux on the high face of the cell, towards - for the low face) and
+ * da(F) = (F_high - F_low) / h_a.  Written out point by point below. */
+int orc_pw_advection(const int64_t* shape, int halo, const double* u, const double* v, const double* w,
+                     double dx, double dy, double dz, double* su, double* sv, double* sw) {
+    og g;
+    if (og_init(&g, 3, shape, halo) || halo < 1) return ORC_EINVAL;
+    const int64_t X = 1, Y = g.s[1], Z = g.s[0];
+#pragma omp parallel for schedule(static)
+    for (int64_t k = halo; k < halo + g.n[0]; k++)
+        for (int64_t j = halo; j < halo + g.n[1]; j++)
+            for (int64_t i = halo; i < halo + g.n[2]; i++) {
+                const int64_t p = k * Z + j * Y + i * X;
+                /* u at (i+1/2, j, k) */
+                {
+                    const double fxh = 0.5 * (u[p] + u[p + X]), fxl = 0.5 * (u[p - X] + u[p]);
+                    const double vyh = 0.5 * (v[p] + v[p + X]), uyh = 0.5 * (u[p] + u[p + Y]);
+                    const double vyl = 0.5 * (v[p - Y] + v[p - Y + X]), uyl = 0.5 * (u[p - Y] + u[p]);
+                    const double wzh = 0.5 * (w[p] + w[p + X]), uzh = 0.5 * (u[p] + u[p + Z]);
+                    const double wzl = 0.5 * (w[p - Z] + w[p - Z + X]), uzl = 0.5 * (u[p - Z] + u[p]);
+                    su[p] = -((fxh * fxh - fxl * fxl) / dx + (vyh * uyh - vyl * uyl) / dy + (wzh * uzh - wzl * uzl) / dz);
+                }
+                /* v at (i, j+1/2, k) */
+                {
+                    const double uxh = 0.5 * (u[p] + u[p + Y]), vxh = 0.5 * (v[p] + v[p + X]);
+                    const double uxl = 0.5 * (u[p - X] + u[p - X + Y]), vxl = 0.5 * (v[p - X] + v[p]);
+                    const double fyh = 0.5 * (v[p] + v[p + Y]), fyl = 0.5 * (v[p - Y] + v[p]);
+                    const double wzh = 0.5 * (w[p] + w[p + Y]), vzh = 0.5 * (v[p] + v[p + Z]);
+                    const double wzl = 0.5 * (w[p - Z] + w[p - Z + Y]), vzl = 0.5 * (v[p - Z] + v[p]);
+                    sv[p] = -((uxh * vxh - uxl * vxl) / dx + (fyh * fyh - fyl * fyl) / dy + (wzh * vzh - wzl * vzl) / dz);
+                }
+                /* w at (i, j, k+1/2) */
+                {
+                    const double uxh = 0.5 * (u[p] + u[p + Z]), wxh = 0.5 * (w[p] + w[p + X]);
+                    const double uxl = 0.5 * (u[p - X] + u[p - X + Z]), wxl = 0.5 * (w[p - X] + w[p]);
+                    const double vyh = 0.5 * (v[p] + v[p + Z]), wyh = 0.5 * (w[p] + w[p + Y]);
+                    const double vyl = 0.5 * (v[p - Y] + v[p - Y + Z]), wyl = 0.5 * (w[p - Y] + w[p]);
+                    const double fzh = 0.5 * (w[p] + w[p + Z]), fzl = 0.5 * (w[p - Z] + w[p]);
+                    sw[p] = -((uxh * wxh - uxl * wxl) / dx + (vyh * wyh - vyl * wyl) / dy + (fzh * fzh - fzl * fzl) / dz);
+                }
+            }
+    return ORC_OK;
 }
 
 int orc_abi_version(void) { return 1; }

@@ -191,13 +191,15 @@ class Plan:
         return fields
 
     # exchanges
-    def exchanges(self, grid, coord, periodic=False):
-        arr = (Exchange * 6)()
-        n = C.c_int(6)
+    def exchanges(self, grid, coord, periodic=False, box=False):
+        """Exchange declarations of the rank at `coord`: faces, or with
+        box=True faces, edges and corners (stencil_exchanges_box)."""
+        arr = (Exchange * 26)()
+        n = C.c_int(26)
         g = (C.c_int32 * 3)(*[int(x) for x in grid] + [1] * (3 - len(grid)))
         cc = (C.c_int32 * 3)(*[int(x) for x in coord] + [0] * (3 - len(coord)))
-        call("stencil_exchanges", self._h, g, cc, int(periodic), C.cast(arr, C.c_void_p),
-             C.byref(n))
+        call("stencil_exchanges_box" if box else "stencil_exchanges", self._h, g, cc, int(periodic),
+             C.cast(arr, C.c_void_p), C.byref(n))
         return [arr[i] for i in range(n.value)]
 
     def exchange_elems(self, ex) -> int:

@@ -35,6 +35,12 @@ class Exchange(C.Structure):
                 "src_offset": list(self.src_offset[:ndim]), "to": list(self.to[:ndim])}
 
 
+class Term(C.Structure):
+    """stencil_term: out += coeff * in[0](i + off[0]) (* in[1](i + off[1]))."""
+    _fields_ = [("out", C.c_int32), ("nfac", C.c_int32), ("inp", C.c_int32 * 2),
+                ("off", (C.c_int32 * 3) * 2), ("coeff", C.c_double)]
+
+
 class Source(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p)]
 
@@ -45,7 +51,8 @@ class Receivers(C.Structure):
 
 EXPORTS = [
     "stencil_create", "stencil_destroy", "stencil_layout", "stencil_apply", "stencil_run",
-    "stencil_exchanges", "stencil_halo_pack", "stencil_halo_unpack", "stencil_batch_create",
+    "stencil_exchanges", "stencil_exchanges_box", "stencil_halo_pack", "stencil_halo_unpack",
+    "stencil_program_create", "stencil_program_apply", "stencil_batch_create",
     "stencil_batch_layout", "stencil_batch_run", "stencil_adjoint_workspace",
     "stencil_forward_ckpt", "stencil_adjoint", "stencil_wave_beta", "stencil_variant_count",
     "stencil_variant_name", "stencil_get_variant", "stencil_set_variant", "stencil_tune",
@@ -74,6 +81,9 @@ def lib():
         "stencil_apply": [P, P, P, P, P, P],
         "stencil_run": [P, P, I64, P, P, P],
         "stencil_exchanges": [P, P, P, I, P, P],
+        "stencil_exchanges_box": [P, P, P, I, P, P],
+        "stencil_program_create": [P, I, P, I, I, I, P, I, I],
+        "stencil_program_apply": [P, P, P, P],
         "stencil_halo_pack": [P, P, P, I, P, P],
         "stencil_halo_unpack": [P, P, P, I, P, P],
         "stencil_batch_create": [P, I, P, I, P, I, I],

@@ -77,6 +77,31 @@ struct TBView {
     uint32_t range;   // bytes of each field's allocation (< 2^31)
 };
 
+// A stencil program: nout outputs, each a sum in program order of terms
+// coeff * in[a](i + o_a) (* in[b](i + o_b)).  Offsets per internal axis
+// (z, y, x), |offset| <= kProgMaxR.
+inline constexpr int kProgMaxTerms = 64, kProgMaxFields = 4, kProgMaxR = 2;
+inline constexpr int kProgTileX = 64, kProgTileY = 16, kProgThreads = 256;
+struct ProgTerm {
+    int out, nfac, in0, in1;
+    int o0[3], o1[3];
+    float coeff;
+};
+struct ProgView {
+    const float* in[kProgMaxFields];
+    float* out[kProgMaxFields];
+    Grid3 g;
+    int nin, nout, nterms;
+    int rz, ry;              // reach of the program along z and y (0 on inactive axes)
+    int ntx, nty, zc, nzc;   // tiling: 64 x 16 tiles, z-chunks
+    ProgTerm t[kProgMaxTerms];
+};
+// dynamic LDS bytes of one workgroup of the program kernel
+inline size_t program_lds_bytes(int nin, int rz, int ry) {
+    return sizeof(float) * (size_t)nin * (2 * rz + 2) * (kProgTileY + 2 * ry) * (kProgTileX + 8);
+}
+hipError_t launch_program(const ProgView& v, hipStream_t s);
+
 // Tile shapes of the z-marching kernel: BX threads along x with VX points
 // each, BY thread rows, each thread owning VY rows (strided by BY); nt: stream
 // the once-read previous level and beta with non-temporal loads and the

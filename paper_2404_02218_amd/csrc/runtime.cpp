@@ -207,6 +207,7 @@ struct PointTables {
 
 struct stencil_plan_s {
     bool batch = false;
+    bool program = false;   // a stencil program plan (stencil_program_create)
     int kind = 0, ndim = 0, radius = 0, halo = 0, dtype = 0, bc = 0;
     int64_t shape[3] = {0, 0, 0};
     double coeffs[5] = {0, 0, 0, 0, 0};
@@ -233,6 +234,9 @@ struct stencil_plan_s {
     std::vector<PointTables> shot_src_ext;
     std::vector<DevBuf> shot_tb;   // 2 per shot
     DevTable tbviews[2];
+    // stencil program
+    int nin = 0, nout = 0, reach[3] = {0, 0, 0};
+    std::vector<ProgTerm> pterms;
 
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -267,9 +271,17 @@ bool tb_batch_supported(const stencil_plan_s* p) {
 }
 
 int variant_count_of(const stencil_plan_s* p) {
+    if (p->program) return 1;
     if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
     if (p->ndim != 3) return 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
+}
+
+// plans of the sweep entry points (not stencil programs)
+stencil_status check_sweep_plan(stencil_plan p) {
+    ST_TRY(check_plan(p, false));
+    if (p->program) return fail(STENCIL_E_STATE, "a stencil program plan takes stencil_program_apply");
+    return STENCIL_OK;
 }
 
 stencil_status check_ptr(const void* p, const char* what) {
@@ -399,35 +411,64 @@ void set_tiling(ZView& v, const Layout& L, const Variant& var) {
 // box of the exchange facing the opposite way (internal z, y, x axes).
 void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out);
 
+// Exchange declarations of one rank: per axis and side, the r-thick face
+// (star); with `box`, every neighbour direction d in {-1,0,1}^ndim \ {0}, so
+// edges and corners too, in C order of d.
 stencil_status exchanges_for(const Layout& L, int radius, const int32_t* grid, const int32_t* coord, int periodic,
-                             std::vector<stencil_exchange>& ex) {
+                             std::vector<stencil_exchange>& ex, bool box = false) {
     ex.clear();
     for (int i = 0; i < L.ndim; i++) {
         if (grid[i] < 1 || coord[i] < 0 || coord[i] >= grid[i])
             return fail(STENCIL_E_INVALID, "rank coordinate outside the rank grid");
     }
-    for (int i = 0; i < L.ndim; i++) {
-        for (int side = 0; side < 2; side++) {
-            const bool has = periodic || (side == 0 ? coord[i] > 0 : coord[i] < grid[i] - 1);
-            if (!has) continue;
-            stencil_exchange e;
-            std::memset(&e, 0, sizeof(e));
-            for (int j = 0; j < L.ndim; j++) {
-                e.at[j] = L.halo;
-                e.size[j] = L.g.n[3 - L.ndim + j];
-            }
-            e.size[i] = radius;
-            if (side == 0) {
-                e.at[i] = L.halo - radius;
-                e.src_offset[i] = radius;
-                e.to[i] = -1;
+    auto make = [&](const int* d) {
+        stencil_exchange e;
+        std::memset(&e, 0, sizeof(e));
+        for (int j = 0; j < L.ndim; j++) {
+            const int64_t n = L.g.n[3 - L.ndim + j];
+            if (d[j] < 0) {
+                e.at[j] = L.halo - radius;
+                e.size[j] = radius;
+                e.src_offset[j] = radius;
+            } else if (d[j] > 0) {
+                e.at[j] = L.halo + n;
+                e.size[j] = radius;
+                e.src_offset[j] = -radius;
             } else {
-                e.at[i] = L.halo + L.g.n[3 - L.ndim + i];
-                e.src_offset[i] = -radius;
-                e.to[i] = 1;
+                e.at[j] = L.halo;
+                e.size[j] = n;
             }
-            ex.push_back(e);
+            e.to[j] = d[j];
         }
+        ex.push_back(e);
+    };
+    auto has = [&](const int* d) {
+        for (int j = 0; j < L.ndim; j++) {
+            if (d[j] < 0 && !periodic && coord[j] == 0) return false;
+            if (d[j] > 0 && !periodic && coord[j] == grid[j] - 1) return false;
+        }
+        return true;
+    };
+    if (!box) {
+        for (int i = 0; i < L.ndim; i++)
+            for (int side = 0; side < 2; side++) {
+                int d[3] = {0, 0, 0};
+                d[i] = side == 0 ? -1 : 1;
+                if (has(d)) make(d);
+            }
+        return STENCIL_OK;
+    }
+    int ndir = 1;
+    for (int i = 0; i < L.ndim; i++) ndir *= 3;
+    for (int code = 0; code < ndir; code++) {
+        int d[3] = {0, 0, 0}, rem = code;
+        bool zero = true;
+        for (int i = L.ndim - 1; i >= 0; i--) {
+            d[i] = rem % 3 - 1;
+            rem /= 3;
+            zero &= d[i] == 0;
+        }
+        if (!zero && has(d)) make(d);
     }
     return STENCIL_OK;
 }
@@ -676,7 +717,7 @@ stencil_status stencil_layout(stencil_plan plan, int64_t* extents, int64_t* stri
 
 stencil_status stencil_apply(stencil_plan p, void* out, const void* const* in, const int64_t* lo, const int64_t* hi,
                              void* stream) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     if (!in) return fail(STENCIL_E_INVALID, "in is NULL");
     ST_TRY(check_ptr(out, "out"));
     ST_TRY(check_ptr(in[0], "in[0]"));
@@ -759,7 +800,7 @@ static stencil_status ensure_tb_pair(stencil_plan p) {
 
 stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     ST_TRY(run_args(p, fields, nsteps, src, rec));
     ST_TRY(prepare_points(p, src, rec));
     hipStream_t s = (hipStream_t)stream;
@@ -827,6 +868,115 @@ stencil_status stencil_exchanges(stencil_plan p, const int32_t* grid, const int3
     if (out)
         for (size_t i = 0; i < ex.size(); i++) out[i] = ex[i];
     *n = (int)ex.size();
+    return STENCIL_OK;
+}
+
+stencil_status stencil_exchanges_box(stencil_plan p, const int32_t* grid, const int32_t* coord, int periodic,
+                                     stencil_exchange* out, int* n) {
+    ST_TRY(check_plan(p, false));
+    if (!grid || !coord || !n) return fail(STENCIL_E_INVALID, "grid, coord and n must be non-NULL");
+    std::vector<stencil_exchange> ex;
+    ST_TRY(exchanges_for(p->L, p->radius, grid, coord, periodic, ex, true));
+    if (out && *n < (int)ex.size()) return fail(STENCIL_E_INVALID, "capacity of `out` is too small");
+    if (out)
+        for (size_t i = 0; i < ex.size(); i++) out[i] = ex[i];
+    *n = (int)ex.size();
+    return STENCIL_OK;
+}
+
+stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t* shape, int halo, int nin,
+                                      int nout, const stencil_term* terms, int nterms, stencil_dtype dtype) {
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (ndim < 1 || ndim > 3) return fail(ndim > 3 ? STENCIL_E_UNSUPPORTED : STENCIL_E_INVALID, "ndim must be 1, 2 or 3");
+    if (!shape) return fail(STENCIL_E_INVALID, "shape is NULL");
+    if (dtype != STENCIL_F32) return fail(STENCIL_E_UNSUPPORTED, "stencil programs take FP32 storage");
+    if (halo < 1 || halo > 64) return fail(STENCIL_E_INVALID, "halo must be in [1, 64]");
+    if (nin < 1 || nout < 1) return fail(STENCIL_E_INVALID, "nin and nout must be >= 1");
+    if (nin > kProgMaxFields || nout > kProgMaxFields)
+        return fail(STENCIL_E_UNSUPPORTED, "at most 4 input and 4 output fields");
+    if (!terms || nterms < 1) return fail(STENCIL_E_INVALID, "a program needs at least one term");
+    if (nterms > kProgMaxTerms) return fail(STENCIL_E_UNSUPPORTED, "at most 64 terms");
+    const int lim = std::min(halo, kProgMaxR);
+    std::vector<ProgTerm> pt((size_t)nterms);
+    int reach[3] = {0, 0, 0};
+    for (int t = 0; t < nterms; t++) {
+        const stencil_term& T = terms[t];
+        if (T.out < 0 || T.out >= nout) return fail(STENCIL_E_INVALID, "term output index out of range");
+        if (T.nfac < 1 || T.nfac > 2) return fail(STENCIL_E_INVALID, "a term has 1 or 2 factors");
+        if (!std::isfinite(T.coeff)) return fail(STENCIL_E_INVALID, "term coefficients must be finite");
+        ProgTerm& P = pt[t];
+        P.out = T.out;
+        P.nfac = T.nfac;
+        P.coeff = (float)T.coeff;
+        for (int f = 0; f < 2; f++) {
+            const bool used = f < T.nfac;
+            const int in = used ? T.in[f] : 0;
+            if (used && (in < 0 || in >= nin)) return fail(STENCIL_E_INVALID, "term input index out of range");
+            int* o = f == 0 ? P.o0 : P.o1;
+            for (int a = 0; a < 3; a++) {
+                const int off = used ? T.off[f][a] : 0;
+                if (a < 3 - ndim && off != 0) return fail(STENCIL_E_INVALID, "offset along an axis the grid lacks");
+                if (off < -lim || off > lim)
+                    return fail(off < -halo || off > halo ? STENCIL_E_INVALID : STENCIL_E_UNSUPPORTED,
+                                "offsets must lie within min(halo, 2)");
+                o[a] = off;
+                reach[a] = std::max(reach[a], std::abs(off));
+            }
+            if (f == 0) P.in0 = in;
+            else P.in1 = in;
+        }
+    }
+    stencil_plan p = new (std::nothrow) stencil_plan_s();
+    if (!p) return fail(STENCIL_E_NOMEM, "out of host memory");
+    p->program = true;
+    p->kind = -1;
+    p->ndim = ndim;
+    p->halo = halo;
+    p->dtype = dtype;
+    p->nin = nin;
+    p->nout = nout;
+    p->pterms = pt;
+    for (int a = 0; a < 3; a++) p->reach[a] = reach[a];
+    p->radius = std::max(1, std::max(reach[0], std::max(reach[1], reach[2])));
+    for (int i = 0; i < ndim; i++) p->shape[i] = shape[i];
+    stencil_status st = make_layout(ndim, shape, halo, dtype, p->L);
+    if (st != STENCIL_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_program_apply(stencil_plan p, void* const* outs, const void* const* ins, void* stream) {
+    ST_TRY(check_plan(p, false));
+    if (!p->program) return fail(STENCIL_E_STATE, "not a stencil program plan");
+    if (!outs || !ins) return fail(STENCIL_E_INVALID, "outs and ins must be non-NULL");
+    for (int f = 0; f < p->nin; f++) ST_TRY(check_ptr(ins[f], "input field"));
+    for (int o = 0; o < p->nout; o++) {
+        ST_TRY(check_ptr(outs[o], "output field"));
+        for (int f = 0; f < p->nin; f++)
+            if (outs[o] == ins[f]) return fail(STENCIL_E_INVALID, "an output aliases an input");
+        for (int q = 0; q < o; q++)
+            if (outs[o] == outs[q]) return fail(STENCIL_E_INVALID, "two outputs alias");
+    }
+    const Layout& L = p->L;
+    ProgView v{};
+    for (int f = 0; f < p->nin; f++) v.in[f] = (const float*)ins[f];
+    for (int o = 0; o < p->nout; o++) v.out[o] = (float*)outs[o];
+    v.g = L.g;
+    v.nin = p->nin;
+    v.nout = p->nout;
+    v.nterms = (int)p->pterms.size();
+    for (size_t t = 0; t < p->pterms.size(); t++) v.t[t] = p->pterms[t];
+    v.rz = p->reach[0];
+    v.ry = p->reach[1];
+    v.ntx = (L.g.n[2] + kProgTileX - 1) / kProgTileX;
+    v.nty = (L.g.n[1] + kProgTileY - 1) / kProgTileY;
+    chunking(L.g.n[0], 64, v.zc, v.nzc);
+    if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) return STENCIL_OK;
+    HIP_TRY(launch_program(v, (hipStream_t)stream));
     return STENCIL_OK;
 }
 
@@ -1198,7 +1348,7 @@ static stencil_status adj_layout(stencil_plan p, int64_t nsteps, int64_t k, AdjL
 static char* slot(void* ws, const AdjLayout& A, int64_t i) { return (char*)ws + i * A.fbytes; }
 
 stencil_status stencil_adjoint_workspace(stencil_plan p, int64_t nsteps, int64_t k, size_t* bytes) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     if (!bytes) return fail(STENCIL_E_INVALID, "bytes is NULL");
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
@@ -1214,7 +1364,7 @@ static Variant adjoint_variant(stencil_plan p) {
 
 stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nsteps, int64_t k, const stencil_source* src,
                                     const stencil_receivers* rec, void* ws, size_t ws_bytes, void* stream) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
     ST_TRY(run_args(p, fields, nsteps, src, rec));
@@ -1256,7 +1406,7 @@ stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nstep
 stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps, int64_t k, const stencil_source* src,
                                const stencil_receivers* rec, const double* resid, const double* rec_scale,
                                double grad_scale, double* grad, void* ws, size_t ws_bytes, void* stream) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
     ST_TRY(check_ptr(beta, "beta"));
@@ -1325,7 +1475,7 @@ stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps,
 }
 
 stencil_status stencil_wave_beta(stencil_plan p, const double* m, double dt, double h, void* beta, void* stream) {
-    ST_TRY(check_plan(p, false));
+    ST_TRY(check_sweep_plan(p));
     if (p->kind != STENCIL_WAVE2) return fail(STENCIL_E_STATE, "not a wave plan");
     if (!m) return fail(STENCIL_E_INVALID, "m is NULL");
     ST_TRY(check_ptr(beta, "beta"));

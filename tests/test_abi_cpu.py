@@ -196,3 +196,65 @@ def test_batch_plan_validation():
     assert list(bp.layouts[1].extents) == [28, 17, 41]
     with pytest.raises(S.StencilError):
         bp.variant = 0
+
+
+def _program(shape=(8, 9, 10), halo=1, nin=2, nout=1, terms=None, dtype=S.F32):
+    from paper_2404_02218_amd.program import Program
+    terms = terms if terms is not None else [(0, 1.0, [(0, (0, 0, 1)), (1, (1, -1, 0))])]
+    return Program(shape, halo, nin, nout, terms, dtype=dtype)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(terms=[(1, 1.0, [(0, (0, 0, 0))])]), -1),                    # output index
+    (dict(terms=[(0, 1.0, [(2, (0, 0, 0))])]), -1),                    # input index
+    (dict(terms=[(0, 1.0, [(0, (0, 0, 2))])]), -1),                    # beyond the halo
+    (dict(halo=4, terms=[(0, 1.0, [(0, (0, 3, 0))])]), -2),            # beyond the kernel's reach
+    (dict(terms=[(0, float("inf"), [(0, (0, 0, 0))])]), -1),
+    (dict(terms=[]), -1),
+    (dict(nin=5), -2),
+    (dict(dtype=S.BF16), -2),
+    (dict(shape=(8, 9), terms=[(0, 1.0, [(0, (1, 0))]), (0, 1.0, [(1, (0, -1))])]), 0),
+])
+def test_program_create_validates(kw, status):
+    if status == 0:
+        p = _program(**kw)
+        assert p.layout.extents == (10, 11)
+        return
+    with pytest.raises(S.StencilError) as e:
+        _program(**kw)
+    assert e.value.status == status
+
+
+def test_program_plans_refuse_sweeps_and_apply_validates():
+    p = _program()
+    lib = _abi.lib()
+    fake = (C.c_void_p * 3)(256, 512, 768)
+    assert lib.stencil_run(p.handle, fake, 1, None, None, None) == -5
+    outs = (C.c_void_p * 1)(256)
+    ins = (C.c_void_p * 2)(256, 512)
+    assert lib.stencil_program_apply(p.handle, outs, ins, None) == -1       # output aliases input
+    ins2 = (C.c_void_p * 2)(512, 769)
+    assert lib.stencil_program_apply(p.handle, outs, ins2, None) == -1      # misaligned input
+    sweep = S.Plan(S.HEAT, (8, 8, 8), 1, [1.0, 1.0])
+    assert lib.stencil_program_apply(sweep.handle, outs, ins, None) == -5
+
+
+@pytest.mark.parametrize("grid,coord,periodic", [([2, 2, 2], [0, 1, 1], False),
+                                                 ([1, 3, 2], [0, 1, 0], False),
+                                                 ([1, 1, 1], [0, 0, 0], True),
+                                                 ([3, 1, 4], [2, 0, 3], True)])
+def test_box_exchange_generator_matches_oracle(grid, coord, periodic):
+    shape, halo = [12, 10, 14], 2
+    p = _program(tuple(shape), halo=halo, terms=[(0, 1.0, [(0, (1, -2, 1))])])
+    mine = [e.as_dict(3) for e in p.exchanges(grid, coord, periodic, box=True)]
+    ref = [e.as_dict(3) for e in oracle.exchanges(shape, halo, 2, grid, coord, periodic, box=True)]
+    assert mine == ref
+
+
+def test_pw_advection_program_shape():
+    from paper_2404_02218_amd.program import pw_advection_terms
+    t = pw_advection_terms(1.0, 2.0, 3.0)
+    assert len(t) == 60
+    assert [sum(1 for o, _, _ in t if o == k) for k in range(3)] == [20, 20, 20]
+    assert all(len(f) == 2 and max(abs(x) for _, off in f for x in off) == 1 or
+               max(abs(x) for _, off in f for x in off) <= 1 for _, _, f in t)

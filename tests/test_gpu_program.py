@@ -1,0 +1,149 @@
+"""GPU parity of stencil programs (stencil_program_apply) and of the box
+exchanges (faces, edges and corners) against the FP64 oracle.
+
+Error bound: an output is a sum of at most T terms, each one or two FP32
+products of FP32 values, accumulated in FP32 in program order, so
+|gpu - exact| <= (T + 2) 2^-24 * M at every point, where M is the same
+program evaluated with |coefficients| and |inputs| (computed by the oracle).
+The oracle's own error is ~1e-16 M."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2404_02218_amd as S
+import workloads as W
+from paper_2404_02218_amd.program import Program, pw_advection_terms
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_program(rng, nin, nout, nterms, r, ndim):
+    terms = []
+    for _ in range(nterms):
+        nfac = int(rng.integers(1, 3))
+        facs = [(int(rng.integers(0, nin)), tuple(int(x) for x in rng.integers(-r, r + 1, size=ndim)))
+                for _ in range(nfac)]
+        terms.append((int(rng.integers(0, nout)), float(rng.standard_normal()), facs))
+    return terms
+
+
+def _embed(a, h):
+    return np.pad(a, h)
+
+
+def _run(prog, arrays):
+    import torch
+    ins = []
+    for a in arrays:
+        f = prog.field()
+        f.load(a)
+        ins.append(f)
+    outs = [prog.field() for _ in range(prog.nout)]
+    prog.apply_program(outs, ins)
+    torch.cuda.synchronize()
+    return [o.to_numpy() for o in outs]
+
+
+def _bound(terms, arrays, h, nout):
+    absterms = [(o, abs(c), facs) for o, c, facs in terms]
+    mag = oracle.program([np.abs(a) for a in arrays], h, nout, absterms)
+    per_out = [sum(1 for o, _, _ in terms if o == k) for k in range(nout)]
+    return [(n + 2) * 2.0 ** -24 * m + 1e-30 for n, m in zip(per_out, mag)]
+
+
+@pytest.mark.parametrize("shape,h,r", [((13, 40, 70), 2, 2), ((9, 17, 130), 2, 1), ((1, 5, 7), 2, 2),
+                                       ((50, 77), 2, 2), ((3, 64, 64), 1, 1)])
+def test_random_programs_meet_the_fp32_bound(device, shape, h, r):
+    rng = np.random.default_rng(hash(shape) % 2 ** 31)
+    ndim = len(shape)
+    terms = _rand_program(rng, 3, 2, 30, r, ndim)
+    arrays = [W.round_to_storage(_embed(rng.standard_normal(shape), h), "f32") for _ in range(3)]
+    prog = Program(shape, h, 3, 2, terms)
+    got = _run(prog, arrays)
+    ref = oracle.program(arrays, h, 2, terms)
+    bnd = _bound(terms, arrays, h, 2)
+    I = (slice(h, -h),) * ndim
+    for g, rf, b in zip(got, ref, bnd):
+        assert np.all(np.abs(g[I] - rf[I]) <= b[I])
+        # interior only: the outputs' halos are untouched (zero)
+        m = np.ones(g.shape, dtype=bool)
+        m[I] = False
+        assert not np.any(g[m])
+
+
+@pytest.mark.parametrize("shape", [(24, 40, 70), (16, 33, 64), (5, 7, 9)])
+def test_pw_advection_program_matches_the_oracle_scheme(device, shape):
+    """The product's 60-term expansion on the GPU against the oracle's direct
+    C-grid formulas, on a periodic velocity (halos filled by wrapping)."""
+    rng = np.random.default_rng(sum(shape))
+    dx, dy, dz = 0.8, 1.1, 0.6
+    vel = [W.round_to_storage(np.pad(rng.standard_normal(shape), 1, mode="wrap"), "f32") for _ in range(3)]
+    terms = pw_advection_terms(dx, dy, dz)
+    prog = Program(shape, 1, 3, 3, terms)
+    got = _run(prog, vel)
+    ref = oracle.pw_advection(*vel, 1, dx, dy, dz)
+    bnd = _bound(terms, vel, 1, 3)
+    I = (slice(1, -1),) * 3
+    for g, rf, b in zip(got, ref, bnd):
+        assert np.all(np.abs(g[I] - rf[I]) <= b[I])
+        assert np.max(np.abs(rf[I])) > 0.1
+
+
+def test_pw_advection_periodic_decomposition_equals_monolithic(device):
+    """2 x 2 x 1 subdomains whose halos (faces, edges, corners) are filled by
+    packing the neighbours' send boxes and unpacking them, on the GPU; the
+    subdomain results equal the whole-domain run with a periodic
+    self-exchange, bit for bit."""
+    import torch
+    shape, grid = (12, 32, 64), [2, 2, 1]
+    sub = tuple(s // g for s, g in zip(shape, grid))
+    rng = np.random.default_rng(77)
+    whole = [W.round_to_storage(rng.standard_normal(shape), "f32") for _ in range(3)]
+    terms = pw_advection_terms(1.0, 1.0, 1.0)
+    mono = Program(shape, 1, 3, 3, terms)
+    mf = []
+    for a in whole:
+        f = mono.field()
+        f.load(_embed(a, 1))
+        ex = mono.exchanges([1, 1, 1], [0, 0, 0], periodic=True, box=True)
+        assert len(ex) == 26
+        # a periodic self-exchange: the receive box of direction d takes the
+        # send box of direction -d (what the neighbour on side d sends back)
+        send = [[x for x in ex if tuple(x.to[:3]) == tuple(-t for t in e.to[:3])][0] for e in ex]
+        buf = torch.empty(mono.exchange_elems(ex), dtype=torch.float32, device=device)
+        mono.pack(f, send, buf)
+        mono.unpack(f, ex, buf)
+        mf.append(f)
+    mo = [mono.field() for _ in range(3)]
+    mono.apply_program(mo, mf)
+    torch.cuda.synchronize()
+    mono_out = [o.to_numpy()[(slice(1, -1),) * 3] for o in mo]
+
+    prog = Program(sub, 1, 3, 3, terms)
+    fields = {}
+    for co in itertools.product(*[range(g) for g in grid]):
+        sl = tuple(slice(c * n, (c + 1) * n) for c, n in zip(co, sub))
+        fs = []
+        for a in whole:
+            f = prog.field()
+            f.load(_embed(a[sl], 1))
+            fs.append(f)
+        fields[co] = fs
+    for co in fields:
+        for k in range(3):
+            for e in prog.exchanges(grid, co, periodic=True, box=True):
+                nb = tuple((c + t) % g for c, t, g in zip(co, e.to[:3], grid))
+                back = [x for x in prog.exchanges(grid, nb, periodic=True, box=True)
+                        if tuple(x.to[:3]) == tuple(-t for t in e.to[:3])][0]
+                buf = torch.empty(prog.exchange_elems([e]), dtype=torch.float32, device=device)
+                prog.pack(fields[nb][k], [back], buf)
+                prog.unpack(fields[co][k], [e], buf)
+    for co, fs in fields.items():
+        outs = [prog.field() for _ in range(3)]
+        prog.apply_program(outs, fs)
+        torch.cuda.synchronize()
+        sl = tuple(slice(c * n, (c + 1) * n) for c, n in zip(co, sub))
+        for o, m in zip(outs, mono_out):
+            assert np.array_equal(o.to_numpy()[(slice(1, -1),) * 3], m[sl]), co

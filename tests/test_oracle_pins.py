@@ -401,3 +401,158 @@ def test_gradient_of_pointwise_perturbation():
         _, Jm, _ = _J_and_grad(P, P["m0"] - dm, dobs)
         fd = (Jp - Jm) / 2
         assert abs(fd - g[pt] * dm[pt]) <= 1e-5 * abs(fd) + 1e-30
+
+
+# ---------------------------------------------------------------- programs
+# The program interpreter and the C-grid advection are pinned to exact
+# integer arithmetic, to the star operator (pinned above), and to the
+# conservation laws of the flux-form advection.
+
+def _wrap(a, h=1):
+    return np.pad(a, h, mode="wrap")
+
+
+def _divergence_free(shape, seed, dx, dy, dz):
+    """A C-grid velocity that is the discrete curl of a random periodic
+    vector potential, so its discrete divergence vanishes."""
+    rng = np.random.default_rng(seed)
+    A1, A2, A3 = (rng.standard_normal(shape) for _ in range(3))
+    back = lambda a, ax: np.roll(a, 1, axis=ax)  # a at index - 1 along ax (periodic)
+    u = (A3 - back(A3, 1)) / dy - (A2 - back(A2, 0)) / dz
+    v = (A1 - back(A1, 0)) / dz - (A3 - back(A3, 2)) / dx
+    w = (A2 - back(A2, 2)) / dx - (A1 - back(A1, 1)) / dy
+    div = (u - back(u, 2)) / dx + (v - back(v, 1)) / dy + (w - back(w, 0)) / dz
+    assert np.abs(div).max() < 1e-12
+    return u, v, w
+
+
+@pytest.mark.parametrize("shape,seed", [((6, 7, 8), 1), ((5, 9, 4), 2), ((8, 8, 8), 3)])
+def test_advection_conserves_momentum_and_kinetic_energy(shape, seed):
+    dx, dy, dz = 1.0, 1.3, 0.7
+    u, v, w = _divergence_free(shape, seed, dx, dy, dz)
+    su, sv, sw = oracle.pw_advection(_wrap(u), _wrap(v), _wrap(w), 1, dx, dy, dz)
+    I = (slice(1, -1),) * 3
+    scale = np.abs(su[I]).sum() + np.abs(sv[I]).sum() + np.abs(sw[I]).sum()
+    assert scale > 1.0
+    # flux form: each momentum component's total is unchanged
+    for s in (su, sv, sw):
+        assert abs(s[I].sum()) <= 1e-13 * scale
+    # centred fluxes of a divergence-free flow do no work: kinetic energy conserved
+    E = (u * su[I] + v * sv[I] + w * sw[I]).sum()
+    assert abs(E) <= 1e-13 * float((np.abs(u * su[I]) + np.abs(v * sv[I]) + np.abs(w * sw[I])).sum())
+    # a flow that is not divergence-free does change the energy (the pin can fail)
+    rng = np.random.default_rng(seed + 10)
+    u2 = u + 0.3 * rng.standard_normal(shape)
+    su2, sv2, sw2 = oracle.pw_advection(_wrap(u2), _wrap(v), _wrap(w), 1, dx, dy, dz)
+    E2 = (u2 * su2[I] + v * sv2[I] + w * sw2[I]).sum()
+    assert abs(E2) > 1e-6 * scale
+
+
+def test_advection_exact_on_a_linear_flow_and_zero_on_a_uniform_one():
+    # u = a x (x = face position), v = w = 0: the x flux term gives
+    # -d(u^2)/dx = -2 a u exactly for centred averages of a linear field
+    n, a, dx = 9, 0.37, 0.5
+    x = (np.arange(-1, n + 1) + 0.5) * dx
+    u = np.broadcast_to(a * x, (n + 2, n + 2, n + 2)).copy()
+    z = np.zeros_like(u)
+    su, sv, sw = oracle.pw_advection(u, z, z, 1, dx, 1.0, 1.0)
+    I = (slice(1, -1),) * 3
+    assert np.allclose(su[I], -2 * a * u[I], rtol=0, atol=1e-12)
+    assert np.all(sv[I] == 0) and np.all(sw[I] == 0)
+    c = np.full((n + 2,) * 3, 1.7)
+    s = oracle.pw_advection(c, -0.4 * np.ones_like(c), 2.1 * np.ones_like(c), 1, 0.3, 0.6, 0.9)
+    assert all(np.abs(q[I]).max() < 1e-12 for q in s)
+
+
+def test_program_interpreter_is_exact_on_integers():
+    # integer inputs and coefficients: every product and sum is exact in FP64,
+    # so the oracle must equal a plain integer evaluation written here
+    rng = np.random.default_rng(7)
+    shape, h = (4, 5, 6), 2
+    ins = [rng.integers(-9, 10, size=tuple(n + 2 * h for n in shape)).astype(np.float64) for _ in range(3)]
+    terms = []
+    for _ in range(25):
+        nfac = int(rng.integers(1, 3))
+        facs = [(int(rng.integers(0, 3)), tuple(int(x) for x in rng.integers(-2, 3, size=3))) for _ in range(nfac)]
+        terms.append((int(rng.integers(0, 2)), float(rng.integers(-5, 6)), facs))
+    outs = oracle.program(ins, h, 2, terms)
+    ref = [np.zeros_like(ins[0]) for _ in range(2)]
+    for z in range(h, h + shape[0]):
+        for y in range(h, h + shape[1]):
+            for x in range(h, h + shape[2]):
+                for o, c, facs in terms:
+                    val = int(c)
+                    for f, (dz, dy, dxx) in facs:
+                        val *= int(ins[f][z + dz, y + dy, x + dxx])
+                    ref[o][z, y, x] += val
+    for a, b in zip(outs, ref):
+        assert np.array_equal(a, b)
+
+
+def test_program_of_the_star_equals_the_star_operator():
+    c = oracle.fd_weights_float(8)
+    shape, h = (7, 8, 9), 4
+    u = np.random.default_rng(8).standard_normal(tuple(n + 2 * h for n in shape))
+    terms = [(0, 3 * c[0], [(0, (0, 0, 0))])]
+    for k in range(1, 5):
+        for ax in range(3):
+            for s in (-1, 1):
+                off = [0, 0, 0]
+                off[ax] = s * k
+                terms.append((0, c[k], [(0, tuple(off))]))
+    got = oracle.program([u], h, 1, terms)[0]
+    ref = oracle.star(u, h, 4, c)
+    I = (slice(h, -h),) * 3
+    assert np.max(np.abs(got[I] - ref[I])) <= 1e-13 * np.max(np.abs(ref[I]))
+
+
+def test_box_exchanges_cover_every_neighbour_direction():
+    shape, h, r = [10, 12, 14], 3, 2
+    ex = oracle.exchanges(shape, h, r, [1, 1, 1], [0, 0, 0], periodic=True, box=True)
+    assert len(ex) == 26
+    dirs = [tuple(e.to[:3]) for e in ex]
+    assert len(set(dirs)) == 26 and (0, 0, 0) not in dirs
+    assert dirs == sorted(dirs)                      # C order of the direction
+    faces = oracle.exchanges(shape, h, r, [1, 1, 1], [0, 0, 0], periodic=True)
+    byd = {tuple(e.to[:3]): e.as_dict(3) for e in ex}
+    for f in faces:                                  # face entries equal the star's
+        assert byd[tuple(f.to[:3])] == f.as_dict(3)
+    corner = byd[(1, -1, 1)]
+    assert corner == {"at": [h + 10, h - r, h + 14], "size": [r, r, r], "src_offset": [-r, r, -r],
+                      "to": [1, -1, 1]}
+    # a corner rank of a non-periodic 2D grid: 2 faces and 1 corner
+    ex2 = oracle.exchanges([8, 8], 1, 1, [2, 2], [0, 0], box=True)
+    assert sorted(tuple(e.to[:2]) for e in ex2) == [(0, 1), (1, 0), (1, 1)]
+
+
+def test_box_exchange_decomposition_equals_monolithic_program():
+    # a periodic 2 x 2 x 1 split of a diagonal-reading program, halos filled
+    # by pack/unpack of the box exchanges, equals the whole-domain program
+    shape, h = (6, 8, 10), 1
+    rng = np.random.default_rng(9)
+    terms = [(0, 0.5, [(0, (0, 1, -1)), (1, (1, 0, 1))]), (0, -1.25, [(1, (-1, -1, 0))]),
+             (1, 2.0, [(0, (1, 1, 1))]), (1, 0.75, [(1, (0, 0, 0)), (0, (-1, 0, 1))])]
+    whole = [rng.standard_normal(shape) for _ in range(2)]
+    ref = oracle.program([_wrap(a) for a in whole], h, 2, terms)
+    grid = [2, 2, 1]
+    sub = [s // g for s, g in zip(shape, grid)]
+    import itertools
+    for co in itertools.product(*[range(g) for g in grid]):
+        sl = tuple(slice(c * n, (c + 1) * n) for c, n in zip(co, sub))
+        fields = []
+        for a in whole:
+            f = np.zeros(tuple(n + 2 * h for n in sub))
+            f[(slice(h, -h),) * 3] = a[sl]
+            # the neighbours' faces, edges and corners arrive via their packs
+            for e in oracle.exchanges(sub, h, 1, grid, co, periodic=True, box=True):
+                nb = [(c + t) % g for c, t, g in zip(co, e.to[:3], grid)]
+                nsl = tuple(slice(c * n, (c + 1) * n) for c, n in zip(nb, sub))
+                nf = np.zeros_like(f)
+                nf[(slice(h, -h),) * 3] = a[nsl]
+                partner = [x for x in oracle.exchanges(sub, h, 1, grid, nb, periodic=True, box=True)
+                           if tuple(x.to[:3]) == tuple(-t for t in e.to[:3])][0]
+                f = oracle.unpack(f, h, [e], oracle.pack(nf, h, [partner]))
+            fields.append(f)
+        got = oracle.program(fields, h, 2, terms)
+        for g_, r_ in zip(got, ref):
+            assert np.array_equal(g_[(slice(h, -h),) * 3], r_[(slice(h, -h),) * 3][sl])
