@@ -299,7 +299,8 @@ def bench_pw(S, W, steps, n=512):
     log(f"[bench] pw advection {n}^3: {ms:.3f} ms, {pts / (ms * 1e-3) / 1e9:.1f} GPts/s")
     return {"interior": list(shape), "terms": len(prog.terms), "GPts_s": round(pts / (ms * 1e-3) / 1e9, 2),
             "ms_per_apply": round(ms, 3), "algorithmic_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-            "bytes_per_point": 24, "kernel": "k_program (60 terms read from LDS)"}
+            "bytes_per_point": 24, "variant": prog.variant_name(prog.variant),
+            "kernel": "stencil_program (compiled with the 60 terms as constants)"}
 
 
 def bench_heat2d(S, W, steps):

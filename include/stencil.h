@@ -249,8 +249,15 @@ typedef struct {
  * plan's layout (stencil_layout), nterms in [1, 64] terms (copied).  Every
  * offset must lie within min(halo, 2).  Errors: STENCIL_E_INVALID for bad
  * indices or offsets, STENCIL_E_UNSUPPORTED for other dtypes or sizes beyond
- * these limits.  stencil_layout, stencil_exchanges(_box), stencil_halo_pack
- * and _unpack and stencil_destroy accept the plan. */
+ * these limits, STENCIL_E_DEVICE if compiling the program's kernel fails
+ * (the message holds the compiler's log).  The plan compiles a kernel in
+ * which the terms are constants (hiprtc, gfx950; plans with the same program
+ * share it, and it is loaded on a device at the first apply there);
+ * stencil_variant_count reports 2: variant 0 runs that kernel, variant 1 a
+ * generic kernel that reads the terms at run time, with identical bits.
+ * stencil_layout, stencil_exchanges(_box), stencil_halo_pack and _unpack,
+ * the variant calls and stencil_destroy accept the plan; stencil_tune
+ * refuses it. */
 stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t* shape, int halo, int nin,
                                       int nout, const stencil_term* terms, int nterms, stencil_dtype dtype);
 
@@ -259,8 +266,8 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
  * written; halos are read from the inputs as they are (refresh them with an
  * exchange first where needed) and outputs' halos are untouched.  No output
  * may alias an input or another output.  Each term evaluates as
- * fl(fl(coeff * a) * b), added to its output's FP32 sum in program order
- * (no fused multiply-add). */
+ * on its output's FP32 sum s in program order: s = fma(coeff, a, s) for
+ * one factor, s = fma(fl(coeff * a), b, s) for two (fma: one rounding). */
 stencil_status stencil_program_apply(stencil_plan plan, void* const* outs, const void* const* ins, void* stream);
 
 /* ------------------------------------------------------------ variants */

@@ -22,7 +22,7 @@ ARCH = os.environ.get("STENCIL_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 SOURCES = ["zmarch_tb.hip", "zmarch_tb_heat.hip", "program.hip", "zmarch_f32.hip", "zmarch_adj.hip", "zmarch_bf16.hip", "zmarch_f16.hip",
-           "kernels.hip", "runtime.cpp"]
+           "kernels.hip", "runtime.cpp", "program_rtc.cpp"]
 
 
 def _compile(src: str) -> str:
@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -6,6 +6,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <string>
+#include <vector>
+
 #include "device.hpp"
 
 namespace stn {
@@ -101,6 +105,13 @@ inline size_t program_lds_bytes(int nin, int rz, int ry) {
     return sizeof(float) * (size_t)nin * (2 * rz + 2) * (kProgTileY + 2 * ry) * (kProgTileX + 8);
 }
 hipError_t launch_program(const ProgView& v, hipStream_t s);
+// the program compiled with its terms as constants (program_rtc.cpp):
+// source text, compilation (shared by equal programs), launch on the
+// current device (loads the code object there once)
+struct RtcProgram;
+std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms);
+std::shared_ptr<RtcProgram> program_compile(const std::string& src, std::string& log);
+hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s);
 
 // Tile shapes of the z-marching kernel: BX threads along x with VX points
 // each, BY thread rows, each thread owning VY rows (strided by BY); nt: stream

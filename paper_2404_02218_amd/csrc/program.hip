@@ -7,7 +7,9 @@
 // plane separates each slot's refill from its last reads.  A thread owns 4
 // consecutive x points of one row and evaluates the terms in program order:
 // a factor's 4 values are one or two aligned 16-byte LDS groups, picked apart
-// by a wave-uniform switch on the x offset.
+// by a wave-uniform switch on the x offset.  This kernel reads the terms at
+// run time; program_rtc.cpp compiles the same tiling and arithmetic with the
+// terms as constants.
 #include "zmarch.hpp"
 
 namespace stn {
@@ -94,22 +96,22 @@ __global__ __launch_bounds__(NT) void k_program(ProgView v) {
                                                                   (ty + ry + o[1]) * LDX + 4 + 4 * tx);
                 return taps4(g, o[2]);
             };
+            // s = fma(c, a, s) for one factor, fma(fl(c a), b, s) for two
             const float4 a = fac(T.in0, T.o0);
-            float4 val = make_float4(__fmul_rn(T.coeff, a.x), __fmul_rn(T.coeff, a.y), __fmul_rn(T.coeff, a.z),
-                                     __fmul_rn(T.coeff, a.w));
+            float4 m = make_float4(T.coeff, T.coeff, T.coeff, T.coeff), b = a;
             if (T.nfac == 2) {
-                const float4 b = fac(T.in1, T.o1);
-                val = make_float4(__fmul_rn(val.x, b.x), __fmul_rn(val.y, b.y), __fmul_rn(val.z, b.z),
-                                  __fmul_rn(val.w, b.w));
+                b = fac(T.in1, T.o1);
+                m = make_float4(__fmul_rn(T.coeff, a.x), __fmul_rn(T.coeff, a.y), __fmul_rn(T.coeff, a.z),
+                                __fmul_rn(T.coeff, a.w));
             }
             // the output index is the same for every lane: a scalar branch
 #pragma unroll
             for (int o = 0; o < kProgMaxFields; o++)
                 if (T.out == o) {
-                    acc[o].x = __fadd_rn(acc[o].x, val.x);
-                    acc[o].y = __fadd_rn(acc[o].y, val.y);
-                    acc[o].z = __fadd_rn(acc[o].z, val.z);
-                    acc[o].w = __fadd_rn(acc[o].w, val.w);
+                    acc[o].x = __builtin_fmaf(m.x, b.x, acc[o].x);
+                    acc[o].y = __builtin_fmaf(m.y, b.y, acc[o].y);
+                    acc[o].z = __builtin_fmaf(m.z, b.z, acc[o].z);
+                    acc[o].w = __builtin_fmaf(m.w, b.w, acc[o].w);
                 }
         }
         if (row_ok) {

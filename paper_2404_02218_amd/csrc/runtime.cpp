@@ -237,6 +237,7 @@ struct stencil_plan_s {
     // stencil program
     int nin = 0, nout = 0, reach[3] = {0, 0, 0};
     std::vector<ProgTerm> pterms;
+    std::shared_ptr<RtcProgram> rtc;   // the compiled program (variant 0)
 
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -271,7 +272,7 @@ bool tb_batch_supported(const stencil_plan_s* p) {
 }
 
 int variant_count_of(const stencil_plan_s* p) {
-    if (p->program) return 1;
+    if (p->program) return 2;
     if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
     if (p->ndim != 3) return 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
@@ -945,6 +946,12 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
         delete p;
         return st;
     }
+    std::string log;
+    p->rtc = program_compile(program_source(nin, nout, reach[0], reach[1], pt), log);
+    if (!p->rtc) {
+        delete p;
+        return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
+    }
     *out = p;
     return STENCIL_OK;
 }
@@ -976,7 +983,8 @@ stencil_status stencil_program_apply(stencil_plan p, void* const* outs, const vo
     v.nty = (L.g.n[1] + kProgTileY - 1) / kProgTileY;
     chunking(L.g.n[0], 64, v.zc, v.nzc);
     if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) return STENCIL_OK;
-    HIP_TRY(launch_program(v, (hipStream_t)stream));
+    if (p->variant == 0) HIP_TRY(launch_program_rtc(*p->rtc, v, (hipStream_t)stream));
+    else HIP_TRY(launch_program(v, (hipStream_t)stream));
     return STENCIL_OK;
 }
 
@@ -1499,7 +1507,11 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
     if (variant < 0 || variant >= n) return fail(STENCIL_E_INVALID, "variant out of range");
     if (!buf || len == 0) return fail(STENCIL_E_INVALID, "buffer is NULL");
     std::string name;
-    if (variant == 0) {
+    const std::string tile = std::to_string(kProgTileX) + "x" + std::to_string(kProgTileY) + "_t" +
+                             std::to_string(kProgThreads);
+    if (p->program) {
+        name = (variant == 0 ? "program_rtc_" : "program_interp_") + tile;
+    } else if (variant == 0) {
         name = "point";
     } else if (variant_of(variant).tb) {
         name = "tb2_" + std::to_string(kTB2TileX) + "x" + std::to_string(kTB2TileY) + "_t" +
@@ -1547,6 +1559,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
     if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
     if (reps < 1 || reps > 1000) return fail(STENCIL_E_INVALID, "reps must be 1..1000");
+    if (p->program) return fail(STENCIL_E_STATE, "stencil_tune takes sweep plans, not stencil programs");
     int nvar = 0;
     ST_TRY(stencil_variant_count(p, &nvar));
     const std::string key = tune_key(p);

@@ -258,3 +258,24 @@ def test_pw_advection_program_shape():
     assert [sum(1 for o, _, _ in t if o == k) for k in range(3)] == [20, 20, 20]
     assert all(len(f) == 2 and max(abs(x) for _, off in f for x in off) == 1 or
                max(abs(x) for _, off in f for x in off) <= 1 for _, _, f in t)
+
+
+def test_program_variants_and_compiled_kernel_limits():
+    """Programs compile (hiprtc, gfx950) at creation: the largest one the
+    limits allow (4 inputs and outputs, reach 2 on every axis, 64 terms: the
+    most LDS) and 1D/2D ones; two variants, and stencil_tune refuses them."""
+    rng = np.random.default_rng(5)
+    for ndim in (1, 2, 3):
+        terms = [(int(rng.integers(0, 4)), float(rng.standard_normal()),
+                  [(int(rng.integers(0, 4)), tuple(int(x) for x in rng.integers(-2, 3, size=ndim)))
+                   for _ in range(int(rng.integers(1, 3)))]) for _ in range(64)]
+        terms[0] = (0, 1.0, [(3, (2,) * ndim), (2, (-2,) * ndim)])
+        p = _program(shape=(7, 9, 11)[3 - ndim:], halo=2, nin=4, nout=4, terms=terms)
+        assert p.variant_count() == 2
+        assert [p.variant_name(v) for v in range(2)] == ["program_rtc_64x16_t256", "program_interp_64x16_t256"]
+        assert p.variant == 0
+        p.variant = 1
+        assert p.variant == 1
+    lib = _abi.lib()
+    fake = (C.c_void_p * 3)(256, 512, 768)
+    assert lib.stencil_tune(p.handle, fake, 1, None) == -5

@@ -2,7 +2,8 @@
 exchanges (faces, edges and corners) against the FP64 oracle.
 
 Error bound: an output is a sum of at most T terms, each one or two FP32
-products of FP32 values, accumulated in FP32 in program order, so
+products of FP32 values, accumulated in FP32 in program order by fused
+multiply-adds (at most two roundings per term), so
 |gpu - exact| <= (T + 2) 2^-24 * M at every point, where M is the same
 program evaluated with |coefficients| and |inputs| (computed by the oracle).
 The oracle's own error is ~1e-16 M."""
@@ -33,8 +34,9 @@ def _embed(a, h):
     return np.pad(a, h)
 
 
-def _run(prog, arrays):
+def _run(prog, arrays, variant=0):
     import torch
+    prog.variant = variant
     ins = []
     for a in arrays:
         f = prog.field()
@@ -62,6 +64,9 @@ def test_random_programs_meet_the_fp32_bound(device, shape, h, r):
     arrays = [W.round_to_storage(_embed(rng.standard_normal(shape), h), "f32") for _ in range(3)]
     prog = Program(shape, h, 3, 2, terms)
     got = _run(prog, arrays)
+    # the compiled kernel (variant 0) and the generic one compute the same bits
+    for a, b in zip(got, _run(prog, arrays, variant=1)):
+        assert np.array_equal(a, b)
     ref = oracle.program(arrays, h, 2, terms)
     bnd = _bound(terms, arrays, h, 2)
     I = (slice(h, -h),) * ndim
@@ -83,6 +88,8 @@ def test_pw_advection_program_matches_the_oracle_scheme(device, shape):
     terms = pw_advection_terms(dx, dy, dz)
     prog = Program(shape, 1, 3, 3, terms)
     got = _run(prog, vel)
+    for a, b in zip(got, _run(prog, vel, variant=1)):
+        assert np.array_equal(a, b)
     ref = oracle.pw_advection(*vel, 1, dx, dy, dz)
     bnd = _bound(terms, vel, 1, 3)
     I = (slice(1, -1),) * 3
