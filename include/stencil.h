@@ -270,6 +270,61 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
  * one factor, s = fma(fl(coeff * a), b, s) for two (fma: one rounding). */
 stencil_status stencil_program_apply(stencil_plan plan, void* const* outs, const void* const* ins, void* stream);
 
+/* ------------------------------------------------------- exchange schedule */
+
+/* The neighbour directions in which a program reads input `field` outside
+ * its interior.  Bit k stands for the direction d (per axis -1, 0 or +1, over
+ * the plan's ndim axes) whose C-order code sum_j (d_j + 1) 3^(ndim-1-j) is k,
+ * the same order as stencil_exchanges_box.  Bit k is set when some term reads
+ * the field at an offset o that lands in d's halo box from some interior
+ * point: on every axis d_j = sign(o_j) with o_j != 0, or d_j = 0 with
+ * |o_j| < n_j.  Exchanging these boxes is enough before an apply (the paper's
+ * dmp.swap, Section 4.2, restricted to what the access pattern needs).
+ * Errors: STENCIL_E_STATE for a sweep plan, STENCIL_E_INVALID for a bad
+ * field index. */
+stencil_status stencil_program_halo_dirs(stencil_plan plan, int field, uint32_t* dirs);
+
+/* One apply of a sequence: a program plan and the ids (0 .. nfields-1) of
+ * the fields bound to its inputs and outputs. */
+typedef struct {
+    stencil_plan program;
+    int32_t in[4];  /* first nin entries used */
+    int32_t out[4]; /* first nout entries used */
+} stencil_step;
+
+enum { STENCIL_ACT_EXCHANGE = 0, STENCIL_ACT_APPLY = 1 };
+
+/* One action of a schedule.  An exchange refreshes the halo boxes of `field`
+ * in `dirs` (bits as stencil_program_halo_dirs) from the field's current
+ * interior; `step` is the step whose read it serves first (-1 in a
+ * prologue).  An apply runs `step`. */
+typedef struct {
+    int32_t kind;
+    int32_t step;
+    int32_t field;
+    uint32_t dirs;
+} stencil_action;
+
+/* Exchange schedule of a sequence of applies (Section 4.2: a swap before
+ * every load, redundant swaps then removed by data-flow analysis; Section
+ * 4.3: loop-invariant communication hoisted).  A field's halo is stale until
+ * it is exchanged, and again after each apply that writes the field (an apply
+ * writes the interior only).  Before each step, each input field is exchanged
+ * in the directions that step reads and that are stale, widened to every
+ * direction read before the field's next write.  So each field is exchanged
+ * at most once per write, and never when unchanged.  With loop != 0 the steps
+ * are the body of a loop that repeats them.  Reads before a field's first
+ * write in the body see the previous iteration's values.  The exchanges that
+ * make the first iteration equal to every later one go into `prologue`; this
+ * includes every exchange of a field the body never writes (hoisting).  With
+ * loop == 0 the prologue is empty.  Outputs must be distinct and must not be
+ * inputs of the same step, and every program must have the same ndim.
+ * *nprologue and *nbody: in = capacity, out = count.  Errors:
+ * STENCIL_E_INVALID (ids, aliasing, capacity, a sweep plan), STENCIL_E_STATE
+ * (differing ndim). */
+stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfields, int loop,
+                                stencil_action* prologue, int* nprologue, stencil_action* body, int* nbody);
+
 /* ------------------------------------------------------------ variants */
 
 /* Kernel variants of a plan (tile shape and z-chunk of the 3D sweep; variant

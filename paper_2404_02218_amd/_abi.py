@@ -41,6 +41,19 @@ class Term(C.Structure):
                 ("off", (C.c_int32 * 3) * 2), ("coeff", C.c_double)]
 
 
+class Step(C.Structure):
+    """stencil_step: a program plan and the field ids of its inputs and outputs."""
+    _fields_ = [("program", C.c_void_p), ("inp", C.c_int32 * 4), ("out", C.c_int32 * 4)]
+
+
+class Action(C.Structure):
+    """stencil_action: an exchange of `field` in `dirs`, or an apply of `step`."""
+    _fields_ = [("kind", C.c_int32), ("step", C.c_int32), ("field", C.c_int32), ("dirs", C.c_uint32)]
+
+
+ACT_EXCHANGE, ACT_APPLY = 0, 1
+
+
 class Source(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p)]
 
@@ -52,7 +65,8 @@ class Receivers(C.Structure):
 EXPORTS = [
     "stencil_create", "stencil_destroy", "stencil_layout", "stencil_apply", "stencil_run",
     "stencil_exchanges", "stencil_exchanges_box", "stencil_halo_pack", "stencil_halo_unpack",
-    "stencil_program_create", "stencil_program_apply", "stencil_batch_create",
+    "stencil_program_create", "stencil_program_apply", "stencil_program_halo_dirs", "stencil_schedule",
+    "stencil_batch_create",
     "stencil_batch_layout", "stencil_batch_run", "stencil_adjoint_workspace",
     "stencil_forward_ckpt", "stencil_adjoint", "stencil_wave_beta", "stencil_variant_count",
     "stencil_variant_name", "stencil_get_variant", "stencil_set_variant", "stencil_tune",
@@ -84,6 +98,8 @@ def lib():
         "stencil_exchanges_box": [P, P, P, I, P, P],
         "stencil_program_create": [P, I, P, I, I, I, P, I, I],
         "stencil_program_apply": [P, P, P, P],
+        "stencil_program_halo_dirs": [P, I, P],
+        "stencil_schedule": [P, I, I, I, P, P, P, P],
         "stencil_halo_pack": [P, P, P, I, P, P],
         "stencil_halo_unpack": [P, P, P, I, P, P],
         "stencil_batch_create": [P, I, P, I, P, I, I],

@@ -988,6 +988,129 @@ stencil_status stencil_program_apply(stencil_plan p, void* const* outs, const vo
     return STENCIL_OK;
 }
 
+// --------------------------------------------------------- exchange schedule
+// directions (bit = C-order code over the plan's axes) in which a program
+// reads input `field` outside the interior
+static uint32_t program_dirs(const stencil_plan_s* p, int field) {
+    const int nd = p->ndim;
+    uint32_t m = 0;
+    for (const ProgTerm& T : p->pterms)
+        for (int k = 0; k < T.nfac; k++) {
+            if ((k == 0 ? T.in0 : T.in1) != field) continue;
+            const int* o = k == 0 ? T.o0 : T.o1;   // internal axes (z, y, x)
+            // per axis the reachable d: 0 (if |o| < n) and sign(o) (if o != 0)
+            int opts[3][2], nopt[3];
+            for (int j = 0; j < nd; j++) {
+                const int a = 3 - nd + j, off = o[a];
+                nopt[j] = 0;
+                if (std::abs(off) < p->L.g.n[a]) opts[j][nopt[j]++] = 0;
+                if (off != 0) opts[j][nopt[j]++] = off > 0 ? 1 : -1;
+            }
+            int idx[3] = {0, 0, 0};
+            for (;;) {
+                int code = 0;
+                bool zero = true, ok = true;
+                for (int j = 0; j < nd; j++) {
+                    if (nopt[j] == 0) {
+                        ok = false;
+                        break;
+                    }
+                    const int d = opts[j][idx[j]];
+                    code = code * 3 + d + 1;
+                    zero &= d == 0;
+                }
+                if (ok && !zero) m |= 1u << code;
+                int j = nd - 1;
+                while (j >= 0 && ++idx[j] >= nopt[j]) idx[j--] = 0;
+                if (j < 0 || !ok) break;
+            }
+        }
+    return m;
+}
+
+stencil_status stencil_program_halo_dirs(stencil_plan p, int field, uint32_t* dirs) {
+    ST_TRY(check_plan(p, false));
+    if (!p->program) return fail(STENCIL_E_STATE, "not a stencil program plan");
+    if (!dirs) return fail(STENCIL_E_INVALID, "dirs is NULL");
+    if (field < 0 || field >= p->nin) return fail(STENCIL_E_INVALID, "field index out of range");
+    *dirs = program_dirs(p, field);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfields, int loop,
+                                stencil_action* prologue, int* nprologue, stencil_action* body, int* nbody) {
+    if (!nprologue || !nbody) return fail(STENCIL_E_INVALID, "nprologue and nbody must be non-NULL");
+    if (nsteps < 0 || (nsteps > 0 && !steps)) return fail(STENCIL_E_INVALID, "bad step list");
+    if (nfields < 1 || nfields > 4096) return fail(STENCIL_E_INVALID, "nfields must be in [1, 4096]");
+    // reads[k][f]: directions step k reads field f in; writes[k][f]
+    std::vector<std::vector<uint32_t>> reads((size_t)nsteps, std::vector<uint32_t>((size_t)nfields, 0));
+    std::vector<std::vector<char>> writes((size_t)nsteps, std::vector<char>((size_t)nfields, 0));
+    int ndim = -1;
+    for (int k = 0; k < nsteps; k++) {
+        const stencil_plan p = steps[k].program;
+        ST_TRY(check_plan(p, false));
+        if (!p->program) return fail(STENCIL_E_INVALID, "a step's plan is not a stencil program");
+        if (ndim >= 0 && p->ndim != ndim) return fail(STENCIL_E_STATE, "the programs differ in ndim");
+        ndim = p->ndim;
+        for (int i = 0; i < p->nin; i++) {
+            const int f = steps[k].in[i];
+            if (f < 0 || f >= nfields) return fail(STENCIL_E_INVALID, "input field id out of range");
+            reads[k][f] |= program_dirs(p, i);
+        }
+        for (int o = 0; o < p->nout; o++) {
+            const int f = steps[k].out[o];
+            if (f < 0 || f >= nfields) return fail(STENCIL_E_INVALID, "output field id out of range");
+            for (int i = 0; i < p->nin; i++)
+                if (steps[k].in[i] == f) return fail(STENCIL_E_INVALID, "a step's output is one of its inputs");
+            if (writes[k][f]) return fail(STENCIL_E_INVALID, "a step writes one field twice");
+            writes[k][f] = 1;
+        }
+    }
+    // directions read of f from step k on, up to its next write (wrapping
+    // into the next iteration of a loop, at most once around)
+    auto need_from = [&](int k, int f) {
+        uint32_t m = 0;
+        for (int i = 0; i < (loop ? nsteps : nsteps - k); i++) {
+            const int j = (k + i) % nsteps;
+            if (writes[j][f]) break;
+            m |= reads[j][f];
+        }
+        return m;
+    };
+    auto simulate = [&](std::vector<uint32_t> fresh, std::vector<stencil_action>* out) {
+        for (int k = 0; k < nsteps; k++) {
+            for (int f = 0; f < nfields; f++)
+                if (reads[k][f] & ~fresh[f]) {
+                    const uint32_t d = need_from(k, f) & ~fresh[f];
+                    if (out) out->push_back(stencil_action{STENCIL_ACT_EXCHANGE, k, f, d});
+                    fresh[f] |= d;
+                }
+            if (out) out->push_back(stencil_action{STENCIL_ACT_APPLY, k, -1, 0});
+            for (int f = 0; f < nfields; f++)
+                if (writes[k][f]) fresh[f] = 0;
+        }
+        return fresh;
+    };
+    std::vector<uint32_t> entry((size_t)nfields, 0);
+    if (loop && nsteps > 0) {
+        // the state at the end of any iteration, restricted to what is read
+        // before the field's first write in the body
+        const std::vector<uint32_t> end = simulate(entry, nullptr);
+        for (int f = 0; f < nfields; f++) entry[f] = end[f] & need_from(0, f);
+    }
+    std::vector<stencil_action> pro, bod;
+    for (int f = 0; f < nfields; f++)
+        if (entry[f]) pro.push_back(stencil_action{STENCIL_ACT_EXCHANGE, -1, f, entry[f]});
+    simulate(entry, &bod);
+    if ((prologue && *nprologue < (int)pro.size()) || (body && *nbody < (int)bod.size()))
+        return fail(STENCIL_E_INVALID, "capacity of an action list is too small");
+    if (prologue) std::copy(pro.begin(), pro.end(), prologue);
+    if (body) std::copy(bod.begin(), bod.end(), body);
+    *nprologue = (int)pro.size();
+    *nbody = (int)bod.size();
+    return STENCIL_OK;
+}
+
 static stencil_status halo_copy(stencil_plan p, void* field, const stencil_exchange* ex, int n, void* buf,
                                 int dir, void* stream) {
     ST_TRY(check_plan(p, false));

@@ -10,9 +10,10 @@ formulas, so the scheme is written here from its definition).
 from __future__ import annotations
 
 import ctypes as C
+from typing import NamedTuple
 
 from . import F32, Plan, _i64
-from ._abi import Term, call
+from ._abi import ACT_EXCHANGE, Action, Step, Term, call
 
 
 def _term_array(terms, ndim):
@@ -68,6 +69,59 @@ class Program(Plan):
         po = (C.c_void_p * self.nout)(*[f.ptr for f in outs])
         pi = (C.c_void_p * self.nin)(*[f.ptr for f in ins])
         call("stencil_program_apply", self._h, po, pi, _stream_ptr(stream))
+
+    def halo_dirs(self, field: int) -> int:
+        """Bit mask of the neighbour directions (C-order codes, as
+        `dir_code`) in which the program reads input `field` outside the
+        interior."""
+        m = C.c_uint32()
+        call("stencil_program_halo_dirs", self._h, int(field), C.byref(m))
+        return m.value
+
+
+def dir_code(to, ndim: int) -> int:
+    """C-order code of a neighbour direction: sum_j (d_j + 1) 3^(ndim-1-j)."""
+    c = 0
+    for j in range(ndim):
+        c = 3 * c + int(to[j]) + 1
+    return c
+
+
+def select(exchanges, dirs: int, ndim: int):
+    """The entries of an exchange list whose direction is in the mask."""
+    return [e for e in exchanges if dirs >> dir_code(e.to, ndim) & 1]
+
+
+class Act(NamedTuple):
+    kind: str      # "exchange" or "apply"
+    step: int      # the step applied, or served first by the exchange (-1: prologue)
+    field: int     # exchanged field id (-1 for an apply)
+    dirs: int      # direction mask of an exchange
+
+
+def schedule(steps, nfields: int, loop: bool = True):
+    """Exchange schedule (stencil_schedule) of a sequence of applies.
+    steps: [(program, input field ids, output field ids)].  Returns
+    (prologue, body), lists of Act."""
+    arr = (Step * max(1, len(steps)))()
+    for k, (prog, ins, outs) in enumerate(steps):
+        if len(ins) != prog.nin or len(outs) != prog.nout:
+            raise ValueError(f"step {k}: expected {prog.nin} inputs and {prog.nout} outputs")
+        arr[k].program = prog.handle
+        for i, f in enumerate(ins):
+            arr[k].inp[i] = int(f)
+        for o, f in enumerate(outs):
+            arr[k].out[o] = int(f)
+    npro, nbod = C.c_int(0), C.c_int(0)
+    call("stencil_schedule", C.cast(arr, C.c_void_p), len(steps), int(nfields), int(bool(loop)), None,
+         C.byref(npro), None, C.byref(nbod))
+    pro, bod = (Action * max(1, npro.value))(), (Action * max(1, nbod.value))()
+    call("stencil_schedule", C.cast(arr, C.c_void_p), len(steps), int(nfields), int(bool(loop)),
+         C.cast(pro, C.c_void_p), C.byref(npro), C.cast(bod, C.c_void_p), C.byref(nbod))
+
+    def conv(a):
+        return Act("exchange" if a.kind == ACT_EXCHANGE else "apply", a.step, a.field, a.dirs)
+    return [conv(pro[i]) for i in range(npro.value)], [conv(bod[i]) for i in range(nbod.value)]
 
 
 def _product(a, b, scale):
