@@ -303,6 +303,73 @@ def bench_pw(S, W, steps, n=512):
             "kernel": "stencil_program (compiled with the 60 terms as constants)"}
 
 
+def bench_pw_loop(S, W, iters, n=512):
+    """A forward-Euler loop of the PW advection at 512^3 on one periodic rank:
+    per half-iteration one 60-term program (tendencies of u, v, w) and three
+    2-term updates into the other velocity set.  Halos are refreshed by
+    packing and unpacking box exchanges on the device, once with the pruned
+    schedule (stencil_schedule: each velocity once, in the 8 directions PW
+    reads it; tendencies never) and once exchanging all 26 boxes of every
+    input before every apply."""
+    import torch
+    from paper_2404_02218_amd.program import Act, Program, pw_advection_terms, schedule, select
+    shape = (n, n, n)
+    pw = Program(shape, 1, 3, 3, pw_advection_terms(1.0, 1.0, 1.0))
+    upd = Program(shape, 1, 2, 1, [(0, 1.0, [(0, (0, 0, 0))]), (0, 0.01, [(1, (0, 0, 0))])])
+    steps = []
+    for a, b in (((0, 1, 2), (6, 7, 8)), ((6, 7, 8), (0, 1, 2))):
+        steps.append((pw, list(a), [3, 4, 5]))
+        steps += [(upd, [a[c], 3 + c], [b[c]]) for c in range(3)]
+    gen = torch.Generator(device="cuda").manual_seed(W.SEED_BASE + 7)
+    fields = [pw.field() for _ in range(9)]
+    for f in fields[:3]:
+        f.view[1:-1, 1:-1, 1:-1] = torch.rand(shape, generator=gen, device="cuda") - 0.5
+    ex = pw.exchanges([1, 1, 1], [0, 0, 0], periodic=True, box=True)
+    buf = torch.empty(pw.exchange_elems(ex), dtype=torch.float32, device="cuda")
+    full = (1 << 27) - 1 - (1 << 13)
+    naive = []
+    for k, (_, ins, _) in enumerate(steps):
+        naive += [Act("exchange", k, f, full) for f in ins] + [Act("apply", k, -1, 0)]
+    out = {"interior": list(shape), "fields": 9, "steps_per_iteration": len(steps)}
+    for name, (pro, body) in (("scheduled", schedule(steps, 9, loop=True)), ("exchange_all", ([], naive))):
+        plan = []       # boxes resolved before timing
+        elems = 0
+        for a in body:
+            if a.kind == "exchange":
+                sel = select(ex, a.dirs, 3)
+                part = [[x for x in ex if tuple(x.to[:3]) == tuple(-t for t in e.to[:3])][0] for e in sel]
+                plan.append(("x", fields[a.field], sel, part))
+                elems += pw.exchange_elems(sel)
+            else:
+                prog, ins, outs = steps[a.step]
+                plan.append(("a", prog, [fields[f] for f in outs], [fields[f] for f in ins]))
+
+        def run():
+            for it in plan:
+                if it[0] == "x":
+                    pw.pack(it[1], it[3], buf)
+                    pw.unpack(it[1], it[2], buf)
+                else:
+                    it[1].apply_program(it[2], it[3])
+        for a in pro:
+            sel = select(ex, a.dirs, 3)
+            part = [[x for x in ex if tuple(x.to[:3]) == tuple(-t for t in e.to[:3])][0] for e in sel]
+            pw.pack(fields[a.field], part, buf)
+            pw.unpack(fields[a.field], sel, buf)
+        run()
+        with Timer() as t:
+            for _ in range(iters):
+                run()
+        ms = t.ms / iters
+        log(f"[bench] pw loop {name}: {ms:.3f} ms per iteration, {elems * 4 / 2**20:.1f} MiB exchanged")
+        out[name] = {"ms_per_iteration": round(ms, 3), "exchanges_per_iteration":
+                     sum(1 for a in body if a.kind == "exchange"),
+                     "exchanged_MiB_per_iteration": round(elems * 4 / 2 ** 20, 2)}
+    out["speedup"] = round(out["exchange_all"]["ms_per_iteration"] / out["scheduled"]["ms_per_iteration"], 3)
+    del fields, buf
+    return out
+
+
 def bench_heat2d(S, W, steps):
     """2D 5-point heat, 256^2, Dirichlet zero halo, 100 steps: a field of
     260 KiB stays in L2, so this measures launch and synchronisation cost
@@ -567,6 +634,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] pw advection program")
         extras["pw_advection_program"] = bench_pw(S, W, 10)
+        torch.cuda.empty_cache()
+        log("[bench] pw advection loop with scheduled exchanges")
+        extras["pw_advection_loop_exchanges"] = bench_pw_loop(S, W, 5)
         torch.cuda.empty_cache()
         if not args.no_batch:
             log("[bench] batched shots")
