@@ -89,6 +89,24 @@ typedef struct {
     double* trace;
 } stencil_receivers;
 
+/* Interpolated (off-grid) sources and receivers: Devito's sparse functions
+ * (Section 5.1), at real positions instead of grid points.  pos: host,
+ * [n][3] doubles, the first ndim entries used, each a real interior
+ * coordinate in [0, extent - 1] (grid units).  A position spreads over the
+ * 2^ndim corners of its cell with multilinear weights (stencil_interp_weights).
+ * amp: device FP64 [nsteps][n]; trace: device FP64 [nsteps][n]. */
+typedef struct {
+    int64_t n;
+    const double* pos;
+    const double* amp;
+} stencil_source_interp;
+
+typedef struct {
+    int64_t n;
+    const double* pos;
+    double* trace;
+} stencil_receivers_interp;
+
 /* ---------------------------------------------------------------- plans */
 
 /* Create a plan for fields of interior `shape` (ndim 1..3) with a halo of
@@ -134,6 +152,48 @@ stencil_status stencil_apply(stencil_plan plan, void* out, const void* const* in
  * graph per (pointers, nsteps) and replayed. */
 stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream);
+
+/* Absorbing layer for a wave plan (the boundary conditions Devito's
+ * front end provides, Section 5.1): the sweep becomes the damped leapfrog
+ *     u^{t+1} = (2u^t - (1 - g) u^{t-1} + beta .* L u^t) / (1 + g)
+ * (m u_tt + eta u_t = laplace(u)/h^2 with centred u_t and g = eta dt / (2m)),
+ * evaluated in FP32 as ((2u - u_prev) + g u_prev + beta L u) / (1 + g); where
+ * g = 0 the update is the undamped one bit for bit.  g is separable: profile
+ * is a host array of extent_0 + ... + extent_{ndim-1} doubles (the per-axis
+ * profiles one after another in axis order), g at a point = the sum of its
+ * coordinates' entries (added first axis first, in FP32).  Sources are added
+ * after the damped update as before.  NULL removes the layer.  The plan then
+ * runs the z-marching and point kernels only (no temporally blocked
+ * variants; a selected one reverts to the default), and the adjoint path
+ * refuses it.  Errors: STENCIL_E_STATE for heat plans,
+ * STENCIL_E_UNSUPPORTED for 16-bit storage, STENCIL_E_INVALID for negative
+ * or non-finite entries. */
+stencil_status stencil_wave_damping(stencil_plan plan, const double* profile);
+
+/* Corners and weights of n interpolated positions (pos as in
+ * stencil_source_interp): corners [n][2^ndim][3] (first ndim entries set)
+ * and weights [n][2^ndim], host arrays.  Per axis with extent e:
+ * base = min(floor(x), e - 2) (0 when e < 2) and f = x - base (0 when
+ * e < 2); corner bit 0 is (base, weight 1 - f), bit 1 is
+ * (min(base + 1, e - 1), weight f).  Corner c has bit (c >> (ndim-1-j)) & 1
+ * on axis j, and its weight is the product of the axes' weights in axis
+ * order.  Host only; errors: STENCIL_E_INVALID for a position outside
+ * [0, e - 1] or not finite. */
+stencil_status stencil_interp_weights(stencil_plan plan, int64_t n, const double* pos, int64_t* corners,
+                                      double* weights);
+
+/* stencil_run with interpolated sources and receivers.  After the sweep of
+ * step t, source s adds w_c * amp[t*n + s] at each corner c, as a point
+ * source of that amount.  Entries at a shared grid point are applied in
+ * (source, corner) order.  Receiver r records trace[t*n + r], the sum over
+ * its corners c in order of w_c * fl64(u^{t+1} at c), as FP64 fused
+ * multiply-adds.  The plan keeps the weights and a corner trace of
+ * nsteps * n * 2^ndim doubles, allocated on first use and reused.  Sweep
+ * plans only (not batched); errors as stencil_run, plus the position errors
+ * of stencil_interp_weights. */
+stencil_status stencil_run_interp(stencil_plan plan, void** fields, int64_t nsteps,
+                                  const stencil_source_interp* src, const stencil_receivers_interp* rec,
+                                  void* stream);
 
 /* ------------------------------------------------------------ exchanges */
 

@@ -63,8 +63,11 @@ def _load():
     lib.orc_pw_advection.argtypes = [P, C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P]
     lib.orc_pack.argtypes = [C.c_int, P, C.c_int, P, P, C.c_int, P]
     lib.orc_unpack.argtypes = [C.c_int, P, C.c_int, P, P, C.c_int, P]
+    lib.orc_interp.argtypes = [C.c_int, P, I64, P, P, P]
+    lib.orc_wave_run_damped.argtypes = [C.c_int, P, C.c_int, C.c_int, P, P, P, P, P, I64, I64, P, P, I64, P, P]
     for f in ("orc_star", "orc_heat_run", "orc_wave_run", "orc_wave_adjoint",
-              "orc_wave_gradient", "orc_exchanges", "orc_pack", "orc_unpack"):
+              "orc_wave_gradient", "orc_exchanges", "orc_pack", "orc_unpack", "orc_interp",
+              "orc_wave_run_damped"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -139,6 +142,42 @@ def wave_run(u_n, u_nm1, beta, halo, radius, c, nsteps, src=None, src_amp=None, 
                             _p(beta), _p(a), _p(b), int(nsteps), ns, _p(sp), _p(amp), nr, _p(rp),
                             _p(traces)), "wave_run")
     return a, b, traces
+
+
+def wave_run_damped(u_n, u_nm1, beta, gamma, halo, radius, c, nsteps, src=None, src_amp=None, rec=None):
+    """The damped leapfrog (absorbing layer); gamma is a buffer like beta.
+    Returns (u^N, u^{N-1}, traces[N, nrec])."""
+    lib = _load()
+    a = _f64(u_n).copy()
+    b = _f64(u_nm1).copy()
+    beta, gamma = _f64(beta), _f64(gamma)
+    ndim = a.ndim
+    shape = _shape_of(a, halo)
+    sp, ns = _pos(src, ndim)
+    rp, nr = _pos(rec, ndim)
+    amp = _f64(src_amp).reshape(-1) if ns else None
+    if ns and amp.size < nsteps * ns:
+        raise OracleError("src_amp must hold nsteps x nsrc values")
+    traces = np.zeros((int(nsteps), nr), dtype=np.float64)
+    _check(lib.orc_wave_run_damped(ndim, _p(shape), halo, radius, _p(_coeffs(c)), _p(beta), _p(gamma), _p(a),
+                                   _p(b), int(nsteps), ns, _p(sp), _p(amp), nr, _p(rp), _p(traces)),
+           "wave_run_damped")
+    return a, b, traces
+
+
+def interp(shape, pos):
+    """Corners [n, 2^ndim, ndim] (interior coordinates) and weights
+    [n, 2^ndim] of real positions [n, ndim] (multilinear interpolation)."""
+    lib = _load()
+    ndim = len(shape)
+    p = np.asarray(pos, dtype=np.float64).reshape(-1, ndim)
+    n, nc = p.shape[0], 1 << ndim
+    p3 = np.zeros((max(n, 1), 3))
+    p3[:n, :ndim] = p
+    corners = np.zeros((max(n, 1), nc, 3), dtype=np.int64)
+    w = np.zeros((max(n, 1), nc))
+    _check(lib.orc_interp(ndim, _p(np.asarray(shape, dtype=np.int64)), n, _p(p3), _p(corners), _p(w)), "interp")
+    return corners[:n, :, :ndim], w[:n]
 
 
 def wave_adjoint(beta, halo, radius, c, nsteps, rec, rec_w, resid, probe):

@@ -38,6 +38,17 @@
  *   formulas are printed): the flux-form, centred advection of the velocity
  *   (u, v, w) on a staggered C grid, written out directly in
  *   orc_pw_advection below.
+ *
+ *   Off-grid points (Devito's sparse functions, Section 5.1, at real
+ *   positions): multilinear interpolation over the 2^ndim corners of the
+ *   grid cell holding the position; a source adds weight * amplitude at each
+ *   corner, a receiver records the weighted sum of the corner values.
+ *
+ *   Absorbing layer: the wave equation with a damping term, m u_tt + eta u_t
+ *   = laplace(u) / h^2 + q, central differences in time.  With the
+ *   dimensionless gamma = eta dt / (2 m) per point:
+ *       u^{n+1} = (2 u^n - (1 - gamma) u^{n-1} + beta .* (L u^n)) / (1 + gamma)
+ *   and the sources added after the update as in the undamped step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -656,6 +667,94 @@ int orc_pw_advection(const int64_t* shape, int halo, const double* u, const doub
                     sw[p] = -((uxh * wxh - uxl * wxl) / dx + (vyh * wyh - vyl * wyl) / dy + (fzh * fzh - fzl * fzl) / dz);
                 }
             }
+    return ORC_OK;
+}
+
+/*
+ * Multilinear interpolation over the grid cell of each real position (3
+ * slots per point, the first ndim used, each within [0, n - 1] of its axis).
+ * For axis j with extent e the cell starts at b = min(floor(x), e - 2)
+ * (b = 0 and fraction 0 when e = 1) and the fraction is f = x - b; the lower
+ * corner has weight 1 - f, the upper one (b + 1, or b when e = 1) weight f.
+ * Corner c of a point takes the upper corner on axis j when bit
+ * (ndim - 1 - j) of c is set; its weight is the product over the axes.
+ * corners: [n][2^ndim][3] interior coordinates; weights: [n][2^ndim].
+ */
+int orc_interp(int ndim, const int64_t* shape, int64_t n, const double* pos, int64_t* corners, double* weights) {
+    if (ndim < 1 || ndim > 3 || n < 0 || (n > 0 && (!pos || !corners || !weights))) return ORC_EINVAL;
+    int nc = 1 << ndim;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t lo[3], hi[3];
+        double frac[3];
+        for (int j = 0; j < ndim; j++) {
+            double x = pos[3 * i + j];
+            int64_t e = shape[j];
+            if (!(x >= 0.0 && x <= (double)(e - 1))) return ORC_EINVAL;
+            if (e == 1) {
+                lo[j] = hi[j] = 0;
+                frac[j] = 0.0;
+            } else {
+                int64_t b = (int64_t)floor(x);
+                if (b > e - 2) b = e - 2;
+                lo[j] = b;
+                hi[j] = b + 1;
+                frac[j] = x - (double)b;
+            }
+        }
+        for (int c = 0; c < nc; c++) {
+            double w = 1.0;
+            int64_t* cp = corners + 3 * (i * nc + c);
+            cp[0] = cp[1] = cp[2] = 0;
+            for (int j = 0; j < ndim; j++) {
+                int up = (c >> (ndim - 1 - j)) & 1;
+                cp[j] = up ? hi[j] : lo[j];
+                w *= up ? frac[j] : 1.0 - frac[j];
+            }
+            weights[i * nc + c] = w;
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * The damped leapfrog (see the header): gamma is a full buffer like beta.
+ * Sources and receivers as in orc_wave_run; Dirichlet zero halo.
+ */
+int orc_wave_run_damped(int ndim, const int64_t* shape, int halo, int radius, const double* c,
+                        const double* beta, const double* gamma, double* u_n, double* u_nm1, int64_t nsteps,
+                        int64_t nsrc, const int64_t* src, const double* src_amp, int64_t nrec, const int64_t* rec,
+                        double* traces) {
+    og g;
+    if (og_init(&g, ndim, shape, halo) || check_common(&g, radius) || nsteps < 0 || !gamma) return ORC_EINVAL;
+    if (!pos_list_ok(&g, nsrc, src) || !pos_list_ok(&g, nrec, rec)) return ORC_EINVAL;
+    if ((nsrc > 0 && !src_amp) || (nrec > 0 && !traces)) return ORC_EINVAL;
+    size_t bytes = sizeof(double) * (size_t)g.total;
+    double* a = u_n;
+    double* b = u_nm1;
+    int64_t lz = og_lo(&g, 0), ly = og_lo(&g, 1), lx = og_lo(&g, 2);
+    for (int64_t t = 0; t < nsteps; t++) {
+#pragma omp parallel for schedule(static)
+        for (int64_t z = lz; z < lz + g.n[0]; z++)
+            for (int64_t y = ly; y < ly + g.n[1]; y++)
+                for (int64_t x = lx; x < lx + g.n[2]; x++) {
+                    int64_t p = z * g.s[0] + y * g.s[1] + x;
+                    double lap = star_at(&g, radius, c, a, p);
+                    b[p] = (2.0 * a[p] - (1.0 - gamma[p]) * b[p] + beta[p] * lap) / (1.0 + gamma[p]);
+                }
+        for (int64_t s = 0; s < nsrc; s++) b[og_pos(&g, src + 3 * s)] += src_amp[t * nsrc + s];
+        for (int64_t r = 0; r < nrec; r++) traces[t * nrec + r] = b[og_pos(&g, rec + 3 * r)];
+        double* tmp = a;
+        a = b;
+        b = tmp;
+    }
+    if (a != u_n) {
+        double* tmp = (double*)malloc(bytes);
+        if (!tmp) return ORC_ENOMEM;
+        memcpy(tmp, a, bytes);
+        memcpy(u_nm1, u_n, bytes);
+        memcpy(u_n, tmp, bytes);
+        free(tmp);
+    }
     return ORC_OK;
 }
 

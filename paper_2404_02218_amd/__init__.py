@@ -16,8 +16,8 @@ import numpy as np
 
 from . import _abi
 from ._abi import (BC_DIRICHLET0, BC_PERIODIC, BF16, F16, F32, HEAT, WAVE2,  # noqa: F401
-                   Exchange, Receivers, Source, StencilError, call, lib)
-from .coeffs import heat_weights, second_derivative_weights  # noqa: F401
+                   Exchange, Receivers, ReceiversInterp, Source, SourceInterp, StencilError, call, lib)
+from .coeffs import damping_profile, heat_weights, second_derivative_weights  # noqa: F401
 
 DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
 _ESIZE = {F32: 4, BF16: 2, F16: 2}
@@ -120,6 +120,14 @@ class _Points:
         return Receivers(self.n, self.pos.ctypes.data_as(C.c_void_p), C.c_void_p(self.dev.data_ptr()))
 
 
+def _real_positions(pos, ndim):
+    """[n, ndim] real positions as a C-contiguous [n, 3] float64 array."""
+    p = np.asarray(pos, dtype=np.float64).reshape(-1, ndim)
+    out = np.zeros((p.shape[0], 3), dtype=np.float64)
+    out[:, :ndim] = p
+    return np.ascontiguousarray(out)
+
+
 def _check_f64_device(t, shape, what):
     torch = _torch()
     if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
@@ -185,6 +193,50 @@ class Plan:
             _check_f64_device(rec_trace, (nsteps, rp.n), "rec_trace")
         s, r = sp.source(), rp.receivers()
         call("stencil_run", self._h, ptrs, int(nsteps), C.byref(s) if s else None,
+             C.byref(r) if r else None, _stream_ptr(stream))
+        if ptrs[0] != fields[0].ptr:
+            fields[0], fields[1] = fields[1], fields[0]
+        return fields
+
+    def set_damping(self, profiles):
+        """Absorbing layer (stencil_wave_damping): one 1D array of damping
+        per axis (extent entries each), or None to remove it."""
+        if profiles is None:
+            call("stencil_wave_damping", self._h, None)
+            return
+        if len(profiles) != self.ndim:
+            raise ValueError(f"expected {self.ndim} per-axis profiles")
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1) for p in profiles]))
+        if flat.size != sum(self.shape):
+            raise ValueError("each profile needs one entry per interior point of its axis")
+        call("stencil_wave_damping", self._h, flat.ctypes.data_as(C.c_void_p))
+
+    def interp_weights(self, pos):
+        """Corners [n, 2^ndim, ndim] and weights [n, 2^ndim] of real interior
+        positions [n, ndim] (stencil_interp_weights)."""
+        p = _real_positions(pos, self.ndim)
+        n, nc = p.shape[0], 1 << self.ndim
+        corners = np.zeros((max(n, 1), nc, 3), dtype=np.int64)
+        w = np.zeros((max(n, 1), nc), dtype=np.float64)
+        call("stencil_interp_weights", self._h, n, p.ctypes.data_as(C.c_void_p),
+             corners.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p))
+        return corners[:n, :, :self.ndim], w[:n]
+
+    def run_interp(self, fields: list, nsteps: int, src=None, src_amp=None, rec=None, rec_trace=None,
+                   stream=None):
+        """run() with sources and receivers at real positions [n, ndim]
+        (stencil_run_interp)."""
+        ptrs = (C.c_void_p * 3)(*[f.ptr for f in fields] + [0] * (3 - len(fields)))
+        sp = _real_positions(src, self.ndim) if src is not None else np.zeros((0, 3))
+        rp = _real_positions(rec, self.ndim) if rec is not None else np.zeros((0, 3))
+        s = r = None
+        if len(sp):
+            _check_f64_device(src_amp, (nsteps, len(sp)), "src_amp")
+            s = SourceInterp(len(sp), sp.ctypes.data_as(C.c_void_p), C.c_void_p(src_amp.data_ptr()))
+        if len(rp):
+            _check_f64_device(rec_trace, (nsteps, len(rp)), "rec_trace")
+            r = ReceiversInterp(len(rp), rp.ctypes.data_as(C.c_void_p), C.c_void_p(rec_trace.data_ptr()))
+        call("stencil_run_interp", self._h, ptrs, int(nsteps), C.byref(s) if s else None,
              C.byref(r) if r else None, _stream_ptr(stream))
         if ptrs[0] != fields[0].ptr:
             fields[0], fields[1] = fields[1], fields[0]

@@ -54,6 +54,14 @@ class Action(C.Structure):
 ACT_EXCHANGE, ACT_APPLY = 0, 1
 
 
+class SourceInterp(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p)]
+
+
+class ReceiversInterp(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("trace", C.c_void_p)]
+
+
 class Source(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p)]
 
@@ -64,6 +72,7 @@ class Receivers(C.Structure):
 
 EXPORTS = [
     "stencil_create", "stencil_destroy", "stencil_layout", "stencil_apply", "stencil_run",
+    "stencil_run_interp", "stencil_interp_weights", "stencil_wave_damping",
     "stencil_exchanges", "stencil_exchanges_box", "stencil_halo_pack", "stencil_halo_unpack",
     "stencil_program_create", "stencil_program_apply", "stencil_program_halo_dirs", "stencil_schedule",
     "stencil_batch_create",
@@ -94,6 +103,9 @@ def lib():
         "stencil_layout": [P, P, P, P, P],
         "stencil_apply": [P, P, P, P, P, P],
         "stencil_run": [P, P, I64, P, P, P],
+        "stencil_run_interp": [P, P, I64, P, P, P],
+        "stencil_interp_weights": [P, I64, P, P, P],
+        "stencil_wave_damping": [P, P],
         "stencil_exchanges": [P, P, P, I, P, P],
         "stencil_exchanges_box": [P, P, P, I, P, P],
         "stencil_program_create": [P, I, P, I, I, I, P, I, I],

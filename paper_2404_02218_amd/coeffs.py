@@ -27,3 +27,12 @@ def second_derivative_weights(space_order: int) -> list:
 def heat_weights(space_order: int, alpha: float) -> list:
     """Weights of the explicit heat update u + alpha * L u (alpha = a dt / h^2)."""
     return [alpha * c for c in second_derivative_weights(space_order)]
+
+
+def damping_profile(n: int, width: int, gmax: float):
+    """Per-axis absorbing-layer profile of n points: g = gmax * ((width - d) /
+    width)^2 at distance d < width (in points) from the nearer end, else 0."""
+    import numpy as np
+    d = np.minimum(np.arange(n), np.arange(n)[::-1]).astype(np.float64)
+    return np.where(d < width, gmax * ((width - d) / max(width, 1)) ** 2, 0.0)
+

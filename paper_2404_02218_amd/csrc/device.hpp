@@ -221,6 +221,7 @@ enum Mode : int {
     MODE_WAVE = 1,      // out = 2u - u_prev + beta L u
     MODE_WAVE_D = 2,    // as MODE_WAVE, also writes beta L u (+ source) to a second-difference field
     MODE_WAVE_ADJ = 3,  // as MODE_WAVE, then g += out * d for an imaging field pair (g, d)
+    MODE_WAVE_DAMP = 4, // the wave with an absorbing layer (damped_update), FP32
 };
 
 // Canonical accumulation: centre, then the z pairs, the y pairs, the x pairs,
@@ -241,6 +242,17 @@ __device__ static inline float time_update(float acc, float centre, float prev, 
         float t = 2.0f * centre - prev;
         return fmaf(beta, acc, t);
     }
+}
+
+// The damped leapfrog of an absorbing layer: m u_tt + eta u_t = L u / h^2
+// with u_t centred gives, for gamma = eta dt / (2 m),
+//     u+ = (2u - (1 - gamma) u- + beta L u) / (1 + gamma),
+// evaluated as ((2u - u-) + gamma u- + beta L u) / (1 + gamma).  Where gamma
+// is 0 the result is the undamped update bit for bit.
+__device__ static inline float damped_update(float acc, float centre, float prev, float beta, float gamma) {
+    const float t = 2.0f * centre - prev;
+    if (gamma == 0.0f) return fmaf(beta, acc, t);
+    return fmaf(beta, acc, fmaf(gamma, prev, t)) / (1.0f + gamma);
 }
 
 // source injection: round to storage, widen, add the FP64 amount, round back

@@ -20,6 +20,8 @@
 //  small kernels: source injection / receiver sampling for k_point runs, box
 //            copies (halo pack, unpack, periodic self-exchange), zero fill,
 //            beta from squared slowness, FP64 gradient flush.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace stn {
@@ -66,17 +68,26 @@ __global__ __launch_bounds__(256) void k_point(ZView v, Coefs w, Box3 box) {
         prev = S::load((const T*)v.prev + off);
         beta = S::load((const T*)v.beta + off);
     }
-    S::store((T*)v.out + off, time_update<MODE>(acc, ctr, prev, beta));
+    if constexpr (MODE == MODE_WAVE_DAMP) {
+        const float g = (v.damp[z] + v.damp[v.g.n[0] + y]) + v.damp[v.g.n[0] + v.g.n[1] + x];
+        S::store((T*)v.out + off, damped_update(acc, ctr, prev, beta, g));
+    } else {
+        S::store((T*)v.out + off, time_update<MODE>(acc, ctr, prev, beta));
+    }
 }
 
 // ---------------------------------------------------------- small kernels
 template <typename T>
 __global__ void k_inject(T* base, SrcList src, int arow) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= src.n) return;
-    T* p = base + src.off[s];
-    const double amt = src.amp[(int64_t)arow * src.n + s] * (src.scale ? src.scale[s] : 1.0);
-    Storage<T>::store(p, inject<T>(Storage<T>::load(p), amt));
+    // one thread per distinct position: its entries in index order, as the
+    // z-marching kernels inject them
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= src.ngrp) return;
+    const int b = src.gbeg[g], e = src.gbeg[g + 1];
+    T* p = base + src.off[src.grp[b]];
+    float v = Storage<T>::load(p);
+    for (int k = b; k < e; k++) v = inject<T>(v, src_amount(src, arow, src.grp[k]));
+    Storage<T>::store(p, v);
 }
 
 template <typename T>
@@ -162,6 +173,8 @@ template <typename T>
 static hipError_t point_m(int mode, int radius, const ZView& v, const Coefs& w, const Box3& box, hipStream_t s) {
     if (mode == MODE_HEAT) return point_r<MODE_HEAT, T>(radius, v, w, box, s);
     if (mode == MODE_WAVE) return point_r<MODE_WAVE, T>(radius, v, w, box, s);
+    if constexpr (std::is_same<T, float>::value)
+        if (mode == MODE_WAVE_DAMP) return point_r<MODE_WAVE_DAMP, T>(radius, v, w, box, s);
     return hipErrorInvalidValue;
 }
 
@@ -177,8 +190,8 @@ hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const C
 
 hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& v, const Coefs& w, int parity,
                          int arow, int trow, hipStream_t s) {
-    if (mode == MODE_WAVE_D || mode == MODE_WAVE_ADJ) {
-        // the adjoint path is FP32 only
+    if (mode == MODE_WAVE_D || mode == MODE_WAVE_ADJ || mode == MODE_WAVE_DAMP) {
+        // the adjoint path and the absorbing layer are FP32 only
         if (dtype != DT_F32) return hipErrorInvalidValue;
         return zmarch_adj_f32(mode, radius, cfg, v, w, parity, arow, trow, s);
     }
@@ -208,14 +221,35 @@ hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_vi
 }
 
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s) {
-    if (src.n == 0) return hipSuccess;
-    const unsigned nb = blocks_for(src.n, 64);
+    if (src.ngrp == 0) return hipSuccess;
+    const unsigned nb = blocks_for(src.ngrp, 64);
     switch (dtype) {
         case DT_F32: hipLaunchKernelGGL(k_inject<float>, dim3(nb), dim3(64), 0, s, (float*)out_base + g.origin, src, arow); break;
         case DT_BF16: hipLaunchKernelGGL(k_inject<bf16>, dim3(nb), dim3(64), 0, s, (bf16*)out_base + g.origin, src, arow); break;
         case DT_F16: hipLaunchKernelGGL(k_inject<f16>, dim3(nb), dim3(64), 0, s, (f16*)out_base + g.origin, src, arow); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// interpolated receivers: trace[t][r] = sum over the nc corners c, in order,
+// of w[r][c] * trace8[t][r][c] (FP64)
+__global__ void k_gather(const double* trace8, const double* w, int nc, int64_t n, int64_t rows, double* trace) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * n) return;
+    const int64_t t = i / n, r = i - t * n;
+    const double* v = trace8 + (t * n + r) * nc;
+    double acc = 0.0;
+    for (int c = 0; c < nc; c++) acc = fma(w[r * nc + c], v[c], acc);
+    trace[i] = acc;
+}
+
+hipError_t launch_gather(const double* trace8, const double* w, int nc, int64_t n, int64_t rows, double* trace,
+                         hipStream_t s) {
+    if (n == 0 || rows == 0) return hipSuccess;
+    const int64_t total = n * rows;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, trace8, w, nc, n, rows,
+                       trace);
     return hipGetLastError();
 }
 

@@ -201,8 +201,11 @@ std::map<std::string, int> g_tune_cache;
 // One source/receiver table set (positions are host data, validated)
 struct PointTables {
     DevTable zyx4, tiles, off;
-    int n = 0;
+    DevTable grp, gbeg;           // entries grouped by position (point-kernel injection)
+    int n = 0, ngrp = 0;
     int cfg = -1;
+    int col_shift = 0;            // interpolated sources: entry i uses amplitude column i >> col_shift
+    const double* wscale = nullptr;   // and is scaled by wscale[i]
 };
 
 struct stencil_plan_s {
@@ -218,6 +221,15 @@ struct stencil_plan_s {
     PointTables src, rec, adjrec;
     PointTables src_ext;   // sources listed under every tile within R of them (temporal blocking)
     DevBuf tb_pair[2];     // the second field pair of the temporally blocked sweep (zero halos)
+    // interpolated sources and receivers (stencil_run_interp): corner weights,
+    // the corner trace, and the source mapping applied by prepare_points
+    DevTable interp_sw, interp_rw;
+    // absorbing layer (stencil_wave_damping): FP32 profiles [n0 | n1 | n2]
+    DevTable damp;
+    bool damped = false;
+    DevBuf interp_trace;
+    int interp_shift = 0;
+    const double* interp_w = nullptr;
     DevTable periodic_dummy;
     // graph cache of stencil_run
     hipStream_t cap = nullptr;
@@ -258,7 +270,7 @@ stencil_status check_plan(stencil_plan p, bool want_batch) {
 // storage type) and the 3D heat (FP32), with the zero halo.  Its loads start
 // 8 elements left of a tile and address a field with 32-bit byte offsets.
 bool tb_supported(const stencil_plan_s* p) {
-    if (p->batch || p->ndim != 3 || p->bc != STENCIL_BC_DIRICHLET0) return false;
+    if (p->batch || p->ndim != 3 || p->bc != STENCIL_BC_DIRICHLET0 || p->damped) return false;
     const bool wave = p->kind == STENCIL_WAVE2 && p->radius == 4;
     const bool heat = p->kind == STENCIL_HEAT && p->dtype == STENCIL_F32;
     return (wave || heat) && p->L.g.xlead >= 8 && p->L.bytes < (int64_t(1) << 31);
@@ -333,9 +345,23 @@ void zyx_of(const Layout& L, const int64_t* p3, int out[3]) {
 // point under every tile whose box widened by `ext` in x and y holds it.
 stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T, int ext = 0) {
     T.n = (int)n;
+    T.col_shift = 0;
+    T.wscale = nullptr;
     std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; i++) off[i] = interior_offset(L, pos + 3 * i);
     ST_TRY(T.off.upload(off.data(), sizeof(int64_t) * (size_t)n));
+    {
+        // entries by (position, index): coincident entries are applied in
+        // index order by one thread
+        std::vector<int> grp((size_t)std::max<int64_t>(n, 1)), gbeg(1, 0);
+        for (int64_t i = 0; i < n; i++) grp[i] = (int)i;
+        std::stable_sort(grp.begin(), grp.begin() + n, [&](int a, int b) { return off[a] < off[b]; });
+        for (int64_t k = 1; k <= n; k++)
+            if (k == n || off[grp[k]] != off[grp[k - 1]]) gbeg.push_back((int)k);
+        T.ngrp = (int)gbeg.size() - 1;
+        ST_TRY(T.grp.upload(grp.data(), sizeof(int) * (size_t)n));
+        ST_TRY(T.gbeg.upload(gbeg.data(), sizeof(int) * gbeg.size()));
+    }
     if (cfg >= 0) {
         const int TX = tile_tx(cfg), TY = tile_ty(cfg);
         const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
@@ -380,7 +406,11 @@ SrcList src_list(const PointTables& T, const double* amp, const double* scale) {
     s.tile_begin = (const int*)T.tiles.buf.p;
     s.off = (const int64_t*)T.off.buf.p;
     s.amp = amp;
-    s.scale = scale;
+    s.scale = scale ? scale : T.wscale;
+    s.col_shift = T.col_shift;
+    s.ngrp = T.ngrp;
+    s.grp = (const int*)T.grp.buf.p;
+    s.gbeg = (const int*)T.gbeg.buf.p;
     return s;
 }
 
@@ -598,7 +628,8 @@ stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, i
         var.tb = false;
         var.zmarch = true;
     }
-    const int mode = wave ? MODE_WAVE : MODE_HEAT;
+    const int mode = wave ? (p->damped ? MODE_WAVE_DAMP : MODE_WAVE) : MODE_HEAT;
+    const float* damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
     const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
     const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
     std::vector<CopyList> per;
@@ -614,6 +645,7 @@ stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, i
             v.prev = b;
             v.out = b;
             v.beta = beta;
+            v.damp = damp;
             v.g = L.g;
             set_tiling(v, L, var);
             v.src = sl;
@@ -626,6 +658,7 @@ stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, i
             v.prev = nxt;
             v.out = nxt;
             v.beta = beta;
+            v.damp = damp;
             v.g = L.g;
             Box3 box{};
             for (int a3 = 0; a3 < 3; a3++) {
@@ -749,7 +782,9 @@ stencil_status stencil_apply(stencil_plan p, void* out, const void* const* in, c
     v.beta = wave ? in[2] : nullptr;
     v.out = out;
     v.g = L.g;
-    HIP_TRY(launch_point(wave ? MODE_WAVE : MODE_HEAT, p->radius, p->dtype, v, p->w, box, (hipStream_t)stream));
+    v.damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
+    const int mode = wave ? (p->damped ? MODE_WAVE_DAMP : MODE_WAVE) : MODE_HEAT;
+    HIP_TRY(launch_point(mode, p->radius, p->dtype, v, p->w, box, (hipStream_t)stream));
     return STENCIL_OK;
 }
 
@@ -783,6 +818,10 @@ static stencil_status prepare_points(stencil_plan p, const stencil_source* src, 
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, cfg, p->src));
     if (var.tb) ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src_ext, 4));
     ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
+    for (PointTables* T : {&p->src, &p->src_ext}) {
+        T->col_shift = p->interp_shift;
+        T->wscale = p->interp_w;
+    }
     return STENCIL_OK;
 }
 
@@ -799,9 +838,8 @@ static stencil_status ensure_tb_pair(stencil_plan p) {
     return STENCIL_OK;
 }
 
-stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
-                           const stencil_receivers* rec, void* stream) {
-    ST_TRY(check_sweep_plan(p));
+static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                                 const stencil_receivers* rec, void* stream) {
     ST_TRY(run_args(p, fields, nsteps, src, rec));
     ST_TRY(prepare_points(p, src, rec));
     hipStream_t s = (hipStream_t)stream;
@@ -826,7 +864,13 @@ stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const 
                                     (int64_t)(uintptr_t)p->tb_pair[0].p,
                                     (int64_t)(uintptr_t)p->tb_pair[1].p,
                                     p->src.n,
-                                    p->rec.n};
+                                    p->rec.n,
+                                    (int64_t)(uintptr_t)p->src.wscale,
+                                    p->src.col_shift,
+                                    (int64_t)(uintptr_t)p->src.grp.buf.p,
+                                    (int64_t)(uintptr_t)p->src.gbeg.buf.p,
+                                    (int64_t)p->damped,
+                                    (int64_t)(uintptr_t)p->damp.buf.p};
         if (!p->gexec || key != p->gkey) {
             if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
             if (p->gexec) {
@@ -856,6 +900,119 @@ stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const 
         ST_TRY(enqueue_run(p, a, b, beta, nsteps, src, rec, s));
     }
     if (nsteps & 1) std::swap(fields[0], fields[1]);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_wave_damping(stencil_plan p, const double* profile) {
+    ST_TRY(check_sweep_plan(p));
+    if (p->kind != STENCIL_WAVE2) return fail(STENCIL_E_STATE, "damping applies to wave plans");
+    if (!profile) {
+        p->damped = false;
+        return STENCIL_OK;
+    }
+    if (p->dtype != STENCIL_F32) return fail(STENCIL_E_UNSUPPORTED, "the absorbing layer takes FP32 storage");
+    const Grid3& g = p->L.g;
+    std::vector<float> t((size_t)(g.n[0] + g.n[1] + g.n[2]), 0.f);
+    size_t k = 0, base = 0;
+    for (int a = 0; a < 3; a++) {
+        const bool active = a >= 3 - p->ndim;
+        for (int i = 0; i < g.n[a]; i++) {
+            const double x = active ? profile[k++] : 0.0;
+            if (!std::isfinite(x) || x < 0.0) return fail(STENCIL_E_INVALID, "damping must be finite and >= 0");
+            t[base + (size_t)i] = (float)x;
+        }
+        base += (size_t)g.n[a];
+    }
+    ST_TRY(p->damp.upload(t.data(), sizeof(float) * std::max<size_t>(t.size(), 1)));
+    if (!p->damped && variant_of(p->variant).tb) p->variant = default_variant(p->L);
+    p->damped = true;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                           const stencil_receivers* rec, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    p->interp_shift = 0;
+    p->interp_w = nullptr;
+    return run_common(p, fields, nsteps, src, rec, stream);
+}
+
+// Corners and multilinear weights of real interior positions ([n][3], the
+// first ndim entries used): per axis base = min(floor(x), e - 2) (0 when
+// e < 2), f = x - base; corner bit 0 -> (base, 1 - f), bit 1 ->
+// (min(base + 1, e - 1), f); corners in C order of their bits.
+static stencil_status interp_expand(const Layout& L, int64_t n, const double* pos, std::vector<int64_t>& cpos,
+                                    std::vector<double>& w) {
+    const int nd = L.ndim, nc = 1 << nd;
+    if (n < 0 || n > (int64_t(1) << 24)) return fail(STENCIL_E_INVALID, "point count must be in [0, 2^24]");
+    if (n > 0 && !pos) return fail(STENCIL_E_INVALID, "positions are NULL");
+    cpos.assign((size_t)(n * nc * 3), 0);
+    w.assign((size_t)(n * nc), 0.0);
+    for (int64_t i = 0; i < n; i++) {
+        int64_t base[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+        double f[3] = {0, 0, 0};
+        for (int j = 0; j < nd; j++) {
+            ext[j] = L.g.n[3 - nd + j];
+            const double x = pos[3 * i + j];
+            if (!std::isfinite(x) || x < 0.0 || x > (double)(ext[j] - 1))
+                return fail(STENCIL_E_INVALID, "an interpolated position lies outside the interior");
+            if (ext[j] >= 2) {
+                base[j] = std::min<int64_t>((int64_t)std::floor(x), ext[j] - 2);
+                f[j] = x - (double)base[j];
+            }
+        }
+        for (int c = 0; c < nc; c++) {
+            double wt = 1.0;
+            for (int j = 0; j < nd; j++) {
+                const int bit = (c >> (nd - 1 - j)) & 1;
+                cpos[(size_t)((i * nc + c) * 3 + j)] = bit ? std::min(base[j] + 1, ext[j] - 1) : base[j];
+                wt *= bit ? f[j] : 1.0 - f[j];
+            }
+            w[(size_t)(i * nc + c)] = wt;
+        }
+    }
+    return STENCIL_OK;
+}
+
+stencil_status stencil_interp_weights(stencil_plan p, int64_t n, const double* pos, int64_t* corners,
+                                      double* weights) {
+    ST_TRY(check_plan(p, false));
+    if (!corners || !weights) return fail(STENCIL_E_INVALID, "corners and weights must be non-NULL");
+    std::vector<int64_t> cp;
+    std::vector<double> w;
+    ST_TRY(interp_expand(p->L, n, pos, cp, w));
+    std::copy(cp.begin(), cp.end(), corners);
+    std::copy(w.begin(), w.end(), weights);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_run_interp(stencil_plan p, void** fields, int64_t nsteps, const stencil_source_interp* src,
+                                  const stencil_receivers_interp* rec, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    const int nd = p->ndim, nc = 1 << nd;
+    const int64_t ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+    std::vector<int64_t> sp, rp;
+    std::vector<double> sw, rw;
+    ST_TRY(interp_expand(p->L, ns, src ? src->pos : nullptr, sp, sw));
+    ST_TRY(interp_expand(p->L, nr, rec ? rec->pos : nullptr, rp, rw));
+    if (ns > 0 && !src->amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+    if (nr > 0 && !rec->trace) return fail(STENCIL_E_INVALID, "receiver trace is NULL");
+    if (nsteps < 0 || nsteps > (int64_t(1) << 30)) return fail(STENCIL_E_INVALID, "nsteps out of range");
+    if (nr > 0 && nsteps * nr * nc > (int64_t(1) << 31)) return fail(STENCIL_E_NOMEM, "corner trace too large");
+    ST_TRY(p->interp_sw.upload(sw.data(), sizeof(double) * sw.size()));
+    ST_TRY(p->interp_rw.upload(rw.data(), sizeof(double) * rw.size()));
+    ST_TRY(p->interp_trace.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nsteps * nr * nc)));
+    const stencil_source s8{ns * nc, sp.data(), ns ? src->amp : nullptr};
+    const stencil_receivers r8{nr * nc, rp.data(), (double*)p->interp_trace.p};
+    p->interp_shift = ns ? nd : 0;
+    p->interp_w = ns ? (const double*)p->interp_sw.buf.p : nullptr;
+    const stencil_status st = run_common(p, fields, nsteps, ns ? &s8 : nullptr, nr ? &r8 : nullptr, stream);
+    p->interp_shift = 0;
+    p->interp_w = nullptr;
+    ST_TRY(st);
+    if (nr > 0)
+        HIP_TRY(launch_gather((const double*)p->interp_trace.p, (const double*)p->interp_rw.buf.p, nc, nr, nsteps,
+                              rec->trace, (hipStream_t)stream));
     return STENCIL_OK;
 }
 
@@ -1480,6 +1637,7 @@ static char* slot(void* ws, const AdjLayout& A, int64_t i) { return (char*)ws + 
 
 stencil_status stencil_adjoint_workspace(stencil_plan p, int64_t nsteps, int64_t k, size_t* bytes) {
     ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
     if (!bytes) return fail(STENCIL_E_INVALID, "bytes is NULL");
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
@@ -1496,6 +1654,7 @@ static Variant adjoint_variant(stencil_plan p) {
 stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nsteps, int64_t k, const stencil_source* src,
                                     const stencil_receivers* rec, void* ws, size_t ws_bytes, void* stream) {
     ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
     ST_TRY(run_args(p, fields, nsteps, src, rec));
@@ -1538,6 +1697,7 @@ stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps,
                                const stencil_receivers* rec, const double* resid, const double* rec_scale,
                                double grad_scale, double* grad, void* ws, size_t ws_bytes, void* stream) {
     ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
     AdjLayout A;
     ST_TRY(adj_layout(p, nsteps, k, A));
     ST_TRY(check_ptr(beta, "beta"));
@@ -1668,7 +1828,7 @@ stencil_status stencil_set_variant(stencil_plan p, int variant) {
 
 static std::string tune_key(stencil_plan p) {
     std::string k = std::to_string(p->batch) + ":" + std::to_string(p->kind) + ":" + std::to_string(p->ndim) + ":" +
-                    std::to_string(p->radius) + ":" + std::to_string(p->dtype);
+                    std::to_string(p->radius) + ":" + std::to_string(p->dtype) + ":" + std::to_string(p->damped);
     if (p->batch) {
         for (const Layout& L : p->shots)
             k += ":" + std::to_string(L.g.n[0]) + "x" + std::to_string(L.g.n[1]) + "x" + std::to_string(L.g.n[2]);
@@ -1697,7 +1857,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     if (nvar <= 1) return STENCIL_OK;
     hipStream_t s = (hipStream_t)stream;
     const bool wave = p->kind == STENCIL_WAVE2;
-    const int mode = wave ? MODE_WAVE : MODE_HEAT;
+    const int mode = wave ? (p->damped ? MODE_WAVE_DAMP : MODE_WAVE) : MODE_HEAT;
     // scratch outputs: the caller's fields are only read
     std::vector<const Layout*> Ls;
     if (p->batch)
@@ -1731,6 +1891,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             v.u = fields[i * nf + 0];
             v.prev = wave ? fields[i * nf + 1] : nullptr;
             v.beta = wave ? fields[i * nf + 2] : nullptr;
+            v.damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
             v.out = (char*)scratch + off;
             off += round_up(L.bytes, 256);
             v.g = L.g;

@@ -98,6 +98,14 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         const int y = min(Y0 + ty + j * BY, ymax);
         own[j] = (int64_t)y * sy + min(X0 + VX * tx, xmaxv);
     }
+    // absorbing layer: this thread's rows' and columns' damping profiles
+    float dgy[VY], dgx[VX];
+    if constexpr (MODE == MODE_WAVE_DAMP) {
+#pragma unroll
+        for (int j = 0; j < VY; j++) dgy[j] = v.damp[v.g.n[0] + min(Y0 + ty + j * BY, ny - 1)];
+#pragma unroll
+        for (int i = 0; i < VX; i++) dgx[i] = v.damp[v.g.n[0] + ny + min(X0 + VX * tx + i, nx - 1)];
+    }
     int64_t hoff[NH];
     int hlds[NH];
     bool hon[NH];
@@ -211,6 +219,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
         __syncthreads();
 
+        float dgz = 0.f;
+        if constexpr (MODE == MODE_WAVE_DAMP) dgz = v.damp[z];
         float o[VY][VX];
         float dv[VY][VX];
 #pragma unroll
@@ -265,7 +275,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     p[k - 1] = xv[4 + i + k];
                 }
                 acc = axis_sum<R>(acc, w, m, p);
-                if constexpr (WAVE) {
+                if constexpr (MODE == MODE_WAVE_DAMP) {
+                    o[j][i] = damped_update(acc, ctr, comp(cp[j][c], e), comp(cb[j][c], e),
+                                            (dgz + dgy[j]) + dgx[i]);
+                } else if constexpr (WAVE) {
                     o[j][i] = time_update<MODE>(acc, ctr, comp(cp[j][c], e), comp(cb[j][c], e));
                     if constexpr (MODE == MODE_WAVE_D) dv[j][i] = comp(cb[j][c], e) * acc;
                 } else {
@@ -280,7 +293,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
                 const int dy = e[1] - Y0, dx = e[2] - X0;
                 const int idx = e[3];
-                const double amt = v.src.amp[(int64_t)arow * v.src.n + idx] * (v.src.scale ? v.src.scale[idx] : 1.0);
+                const double amt = src_amount(v.src, arow, idx);
 #pragma unroll
                 for (int j = 0; j < VY; j++)
 #pragma unroll

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import paper_2404_02218_amd as S
+import workloads as W
 from paper_2404_02218_amd import _abi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -279,3 +280,42 @@ def test_program_variants_and_compiled_kernel_limits():
     lib = _abi.lib()
     fake = (C.c_void_p * 3)(256, 512, 768)
     assert lib.stencil_tune(p.handle, fake, 1, None) == -5
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (4, 9), (11,), (1, 6, 5)])
+def test_interp_weights_equal_the_oracle(shape):
+    """stencil_interp_weights (host only) gives the oracle's corners and weights."""
+    rng = np.random.default_rng(sum(shape))
+    nd = len(shape)
+    hi = np.array(shape, dtype=np.float64) - 1
+    pos = rng.uniform(0, 1, size=(30, nd)) * hi
+    pos[0], pos[1] = hi, 0
+    plan = S.Plan(S.WAVE2, shape, 1, [-2.0, 1.0], halo=1)
+    c, w = plan.interp_weights(pos)
+    co, wo = oracle.interp(shape, pos)
+    assert np.array_equal(c, co) and np.array_equal(w, wo)
+    for bad in (-1e-9, hi[0] + 1e-9, float("nan")):
+        p = pos[:1].copy()
+        p[0, 0] = bad
+        with pytest.raises(S.StencilError) as e:
+            plan.interp_weights(p)
+        assert e.value.status == -1
+
+
+def test_damping_validation_and_profile_helper():
+    plan = S.Plan(S.WAVE2, (6, 7, 8), 1, [-2.0, 1.0], halo=1)
+    with pytest.raises(S.StencilError) as e:
+        plan.set_damping([np.zeros(6), np.zeros(7), -np.ones(8)])
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        plan.set_damping([np.zeros(6), np.zeros(7)])
+    with pytest.raises(S.StencilError) as e:
+        S.Plan(S.HEAT, (6, 7, 8), 1, [1.0, 1.0]).set_damping([np.zeros(6), np.zeros(7), np.zeros(8)])
+    assert e.value.status == -5
+    with pytest.raises(S.StencilError) as e:
+        S.Plan(S.WAVE2, (6, 7, 8), 1, [-2.0, 1.0], dtype=S.BF16).set_damping([np.zeros(n) for n in (6, 7, 8)])
+    assert e.value.status == -2
+    for n, width in ((20, 5), (7, 4), (1, 3)):
+        assert np.array_equal(S.damping_profile(n, width, 0.3), W.damping_profiles((n,), width, 0.3)[0])
+    p = S.damping_profile(20, 5, 0.3)
+    assert p[0] == p[-1] == 0.3 and p[5] == 0 and p[4] == pytest.approx(0.3 / 25)

@@ -556,3 +556,67 @@ def test_box_exchange_decomposition_equals_monolithic_program():
         got = oracle.program(fields, h, 2, terms)
         for g_, r_ in zip(got, ref):
             assert np.array_equal(g_[(slice(h, -h),) * 3], r_[(slice(h, -h),) * 3][sl])
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (4, 9), (11,), (1, 6, 5)])
+def test_interp_weights_reproduce_affine_functions(shape):
+    # multilinear weights: non-negative, summing to 1, exact on every affine
+    # function, and a single unit weight at a grid point
+    rng = np.random.default_rng(len(shape) + shape[0])
+    nd = len(shape)
+    hi = np.array(shape, dtype=np.float64) - 1
+    pos = rng.uniform(0, 1, size=(40, nd)) * hi
+    pos[0] = hi                                  # the upper corner of the grid
+    pos[1] = 0
+    pos[2] = np.floor(pos[2])                    # a grid point
+    corners, w = oracle.interp(shape, pos)
+    assert (w >= 0).all() and np.allclose(w.sum(1), 1, rtol=0, atol=1e-15)
+    assert (corners >= 0).all() and (corners <= hi.astype(np.int64)).all()
+    for _ in range(3):
+        a, b = rng.standard_normal(nd), rng.standard_normal()
+        f = lambda x: x @ a + b
+        got = (w * f(corners.astype(np.float64))).sum(1)
+        assert np.allclose(got, f(pos), rtol=0, atol=1e-12)
+    for k in (0, 1, 2):
+        on = w[k] == 1.0
+        assert on.sum() == 1 and np.array_equal(corners[k][on][0], pos[k].astype(np.int64))
+    # every corner lies within one cell of the position
+    assert (np.abs(corners - pos[:, None, :]) <= 1 + 1e-12).all()
+
+
+def test_damped_wave_satisfies_the_discrete_energy_identity():
+    # (u+ - 2u + u-) + g (u+ - u-) = beta L u with L symmetric (zero halo):
+    # E^{n+1/2} - E^{n-1/2} = -sum (g / beta) (u+ - u-)^2, where
+    # E^{n+1/2} = sum (u^{n+1} - u^n)^2 / beta - <u^{n+1}, L u^n>.  A wrong
+    # sign of g, or (1 - g) and (1 + g) swapped, breaks it.
+    shape, h, r = (14, 15, 16), 4, 4
+    c = oracle.fd_weights_float(8)
+    rng = np.random.default_rng(21)
+    I = (slice(h, -h),) * 3
+    pad = lambda a: np.pad(a, h)
+    beta = pad(rng.uniform(0.02, 0.06, size=shape))
+    prof = [np.where(np.minimum(np.arange(n), np.arange(n)[::-1]) < 4,
+                     0.3 * ((4 - np.minimum(np.arange(n), np.arange(n)[::-1])) / 4.0) ** 2, 0.0) for n in shape]
+    gamma = pad(prof[0][:, None, None] + prof[1][None, :, None] + prof[2][None, None, :])
+    u = [pad(rng.standard_normal(shape)), None]
+    u[1] = u[0] + 0.01 * pad(rng.standard_normal(shape))   # (u^{-1}, u^0)
+    levels = [u[0].copy(), u[1].copy()]                       # u^{-1}, u^0, u^1, ...
+    a, b = u[1], u[0]
+    for _ in range(6):
+        a, b, _ = oracle.wave_run_damped(a, b, beta, gamma, h, r, c, 1)
+        levels.append(a.copy())
+    L = lambda x: oracle.star(x, h, r, c)
+
+    def energy(un1, un):
+        return float(((un1 - un)[I] ** 2 / beta[I]).sum() - (un1[I] * L(un)[I]).sum())
+    scale = float((levels[1][I] ** 2 / beta[I]).sum())
+    for n in range(2, len(levels)):
+        up, uc, um = levels[n], levels[n - 1], levels[n - 2]
+        diss = float((gamma[I] / beta[I] * (up - um)[I] ** 2).sum())
+        assert diss > 0
+        assert abs(energy(up, uc) - energy(uc, um) + diss) <= 1e-11 * scale
+    # no damping: the same run as the undamped oracle, bit for bit
+    z = np.zeros_like(gamma)
+    d = oracle.wave_run_damped(u[1], u[0], beta, z, h, r, c, 5)
+    p = oracle.wave_run(u[1], u[0], beta, h, r, c, 5)
+    assert all(np.array_equal(x, y) for x, y in zip(d[:2], p[:2]))

@@ -309,3 +309,15 @@ def inversion_c5(n: int = 256, nsteps: int = 500, nrec: int = 64, h: float = 10.
     w = ricker(np.arange(nsteps) * dt, f0)
     return InversionProblem("adjoint_so8", shape, 4, 4, h, dt, nsteps, checkpoint_every,
                             seed, v0, v_true, src, w, rec)
+
+
+def damping_profiles(shape, width, gmax):
+    """Per-axis absorbing-layer profiles (an input of the damped wave): on
+    each axis, gmax * ((width - d) / width)^2 at distance d < width points
+    from the nearer end, 0 inside."""
+    out = []
+    for n in shape:
+        d = np.minimum(np.arange(n), np.arange(n)[::-1]).astype(np.float64)
+        out.append(np.where(d < width, gmax * ((width - d) / width) ** 2, 0.0))
+    return out
+
