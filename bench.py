@@ -370,6 +370,58 @@ def bench_pw_loop(S, W, iters, n=512):
     return out
 
 
+def bench_absorbing(S, W, steps, n=512, width=40, gmax=0.1):
+    """The headline so-8 wave (512^3, 400 steps, FP32) with a 40-point
+    absorbing layer on every face (quadratic profile, gamma up to 0.1 per
+    axis), its source moved off the grid by (0.5, 0.5, 0.5) cells and 64
+    receivers off the grid on a line 8 cells deep (stencil_run_interp).  The
+    undamped on-grid run at the same variant is timed beside it."""
+    import torch
+    P = W.wave3d_c3(n=n, nsteps=400)
+    plan = S.Plan(S.WAVE2, P.shape, 4, S.second_derivative_weights(8), halo=4)
+    f = [plan.field() for _ in range(3)]
+    f[2].load(W.embed(W.round_to_storage(P.beta, "f32"), 4))
+    plan.set_damping(W.damping_profiles(P.shape, width, gmax))
+    plan.tune(f, reps=3)
+    src = np.minimum(P.src.astype(np.float64) + 0.5, n - 1)
+    rec = np.minimum(W.receiver_line(n, 64, depth=8).astype(np.float64) + np.array([0.25, 0.5, 0.375]), n - 1)
+    amp = torch.from_numpy(P.src_amp).cuda()
+    tr = torch.zeros((P.nsteps, len(rec)), dtype=torch.float64, device="cuda")
+
+    def timed(run):
+        run()
+        with Timer() as t:
+            for _ in range(steps):
+                run()
+        return t.ms / steps
+
+    def damped():
+        f[0].storage.zero_()
+        f[1].storage.zero_()
+        plan.run_interp(f, P.nsteps, src=src, src_amp=amp, rec=rec, rec_trace=tr)
+
+    ms = timed(damped)
+    vname = plan.variant_name(plan.variant)
+    v = plan.variant
+    plan.set_damping(None)
+    plan.variant = v
+
+    def plain():
+        f[0].storage.zero_()
+        f[1].storage.zero_()
+        plan.run(f, P.nsteps, src=P.src, src_amp=amp)
+
+    ms0 = timed(plain)
+    pts = float(n) ** 3 * P.nsteps
+    log(f"[bench] absorbing layer + off-grid points: {ms:.1f} ms ({pts / (ms * 1e-3) / 1e9:.1f} GPts/s), "
+        f"undamped on-grid {ms0:.1f} ms, {vname}")
+    del f
+    return {"interior": [n] * 3, "steps": P.nsteps, "layer_width": width, "gamma_max_per_axis": gmax,
+            "receivers": len(rec), "GPts_s": round(pts / (ms * 1e-3) / 1e9, 2), "ms_per_run": round(ms, 2),
+            "variant": vname, "undamped_ongrid_GPts_s": round(pts / (ms0 * 1e-3) / 1e9, 2),
+            "vs_undamped_same_variant": round(ms0 / ms, 3)}
+
+
 def bench_heat2d(S, W, steps):
     """2D 5-point heat, 256^2, Dirichlet zero halo, 100 steps: a field of
     260 KiB stays in L2, so this measures launch and synchronisation cost
@@ -634,6 +686,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] pw advection program")
         extras["pw_advection_program"] = bench_pw(S, W, 10)
+        torch.cuda.empty_cache()
+        log("[bench] absorbing layer with off-grid source and receivers")
+        extras["wave_absorbing_offgrid"] = bench_absorbing(S, W, max(1, args.steps // 2))
         torch.cuda.empty_cache()
         log("[bench] pw advection loop with scheduled exchanges")
         extras["pw_advection_loop_exchanges"] = bench_pw_loop(S, W, 5)
