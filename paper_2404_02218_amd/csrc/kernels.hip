@@ -20,6 +20,7 @@
 //  small kernels: source injection / receiver sampling for k_point runs, box
 //            copies (halo pack, unpack, periodic self-exchange), zero fill,
 //            beta from squared slowness, FP64 gradient flush.
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -97,24 +98,83 @@ __global__ void k_record(const T* base, RecList rec, int trow) {
     rec.trace[(int64_t)trow * rec.n + r] = (double)Storage<T>::load(base + rec.off[r]);
 }
 
-// element copies between boxes of a field and a contiguous buffer (C order)
+// Box copies between a field and a contiguous buffer (C order within a box,
+// boxes one after another): pack, unpack, and field-to-field (periodic
+// self-exchange).  A workgroup serves one box, so the box's parameters are
+// uniform; a thread copies one unit, 4 elements where the box's rows are
+// 16-byte aligned on both sides (the usual case: faces across x and y start
+// at the aligned interior origin), else 1.  Unit -> (row, column) and
+// row -> (z, y) use 32-bit division by precomputed multipliers.
+struct FastDiv {
+    uint32_t m, s, one;   // q = one ? n : (t + ((n - t) >> 1)) >> s, t = mulhi(n, m)
+};
+
+constexpr int kCopyBoxes = 8;
+struct CopyBox {
+    int64_t src, dst;      // field element offsets of the box's first source / destination element
+    int64_t buf;           // buffer element of the box's first element
+    uint32_t nx, ny, upr, units, vec;   // units per row, units in the box, 4 elements per unit
+    FastDiv by_row, by_y;  // divide by upr, by ny
+};
+struct CopyPlan {
+    int n;
+    uint32_t bstart[kCopyBoxes + 1];   // first workgroup of each box
+    CopyBox box[kCopyBoxes];
+};
+
+static FastDiv fast_div(uint32_t d) {
+    FastDiv f{0, 0, 0};
+    if (d <= 1) {
+        f.one = 1;
+        return f;
+    }
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) l++;
+    f.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    f.s = l - 1;
+    return f;
+}
+
+__device__ static inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    if (f.one) return n;
+    const uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> 1)) >> f.s;
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<uint32_t> { using type = uint4; };
+template <> struct Vec4<uint16_t> { using type = uint2; };
+
 template <typename T, int DIR>
-__global__ void k_boxcopy(T* field, int64_t offset, int64_t s0, int64_t s1, CopyList L, T* buf) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.start[L.n]) return;
+__global__ __launch_bounds__(256) void k_boxcopy(T* __restrict__ field, int64_t s0, int64_t s1, CopyPlan P,
+                                                 T* __restrict__ buf) {
+    using V = typename Vec4<T>::type;
+    const uint32_t blk = blockIdx.x;
     int b = 0;
-    while (b + 1 < L.n && i >= L.start[b + 1]) b++;
-    const int64_t j = i - L.start[b];
-    const int64_t nx = L.size[b][2], ny = L.size[b][1];
-    const int64_t x = j % nx, y = (j / nx) % ny, z = j / (nx * ny);
-    const int64_t src = offset + (L.src[b][0] + z) * s0 + (L.src[b][1] + y) * s1 + (L.src[b][2] + x);
-    const int64_t dst = offset + (L.dst[b][0] + z) * s0 + (L.dst[b][1] + y) * s1 + (L.dst[b][2] + x);
-    if constexpr (DIR == COPY_PACK)
-        buf[i] = field[src];
-    else if constexpr (DIR == COPY_UNPACK)
-        field[dst] = buf[i];
-    else
-        field[dst] = field[src];
+    while (b + 1 < P.n && blk >= P.bstart[b + 1]) b++;
+    const CopyBox& B = P.box[b];
+    const uint32_t u = (blk - P.bstart[b]) * 256u + threadIdx.x;
+    if (u >= B.units) return;
+    const uint32_t row = fdiv(u, B.by_row), col = u - row * B.upr;
+    const uint32_t z = fdiv(row, B.by_y), y = row - z * B.ny;
+    const uint32_t w = B.vec ? 4u : 1u;
+    const int64_t fo = (int64_t)z * s0 + (int64_t)y * s1 + (int64_t)(col * w);
+    const int64_t bo = B.buf + (int64_t)row * B.nx + (int64_t)(col * w);
+    if (B.vec) {
+        if constexpr (DIR == COPY_PACK)
+            *reinterpret_cast<V*>(buf + bo) = *reinterpret_cast<const V*>(field + B.src + fo);
+        else if constexpr (DIR == COPY_UNPACK)
+            *reinterpret_cast<V*>(field + B.dst + fo) = *reinterpret_cast<const V*>(buf + bo);
+        else
+            *reinterpret_cast<V*>(field + B.dst + fo) = *reinterpret_cast<const V*>(field + B.src + fo);
+    } else {
+        if constexpr (DIR == COPY_PACK)
+            buf[bo] = field[B.src + fo];
+        else if constexpr (DIR == COPY_UNPACK)
+            field[B.dst + fo] = buf[bo];
+        else
+            field[B.dst + fo] = field[B.src + fo];
+    }
 }
 
 __global__ void k_zero(uint32_t* p, int64_t n) {
@@ -265,21 +325,64 @@ hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecL
     return hipGetLastError();
 }
 
+template <typename T, int DIR>
+static hipError_t boxcopy_launch(T* f, const Grid3& g, const CopyPlan& P, T* b, hipStream_t s) {
+    if (P.n == 0 || P.bstart[P.n] == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_boxcopy<T, DIR>), dim3(P.bstart[P.n]), dim3(256), 0, s, f, g.s[0], g.s[1], P, b);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t boxcopy_t(int dir, void* field, const Grid3& g, int64_t offset, const CopyList& L, void* buf,
                             hipStream_t s) {
-    const int64_t total = L.start[L.n];
-    if (total == 0) return hipSuccess;
-    const unsigned nb = blocks_for(total, 256);
     T* f = (T*)field;
-    T* b = (T*)buf;
-    if (dir == COPY_PACK)
-        hipLaunchKernelGGL((k_boxcopy<T, COPY_PACK>), dim3(nb), dim3(256), 0, s, f, offset, g.s[0], g.s[1], L, b);
-    else if (dir == COPY_UNPACK)
-        hipLaunchKernelGGL((k_boxcopy<T, COPY_UNPACK>), dim3(nb), dim3(256), 0, s, f, offset, g.s[0], g.s[1], L, b);
-    else
-        hipLaunchKernelGGL((k_boxcopy<T, COPY_FIELD>), dim3(nb), dim3(256), 0, s, f, offset, g.s[0], g.s[1], L, b);
-    return hipGetLastError();
+    T* bp = (T*)buf;
+    auto launch = [&](const CopyPlan& P) -> hipError_t {
+        if (dir == COPY_PACK) return boxcopy_launch<T, COPY_PACK>(f, g, P, bp, s);
+        if (dir == COPY_UNPACK) return boxcopy_launch<T, COPY_UNPACK>(f, g, P, bp, s);
+        return boxcopy_launch<T, COPY_FIELD>(f, g, P, bp, s);
+    };
+    // rows of 4-element units must be 16-byte (4-element) aligned in every
+    // buffer the direction touches
+    const bool buf_ok = dir == COPY_FIELD || ((uintptr_t)buf % (4 * sizeof(T)) == 0);
+    const bool strides_ok = g.s[0] % 4 == 0 && g.s[1] % 4 == 0;
+    constexpr uint32_t kMaxUnits = 1u << 30;
+    CopyPlan P{};
+    for (int k = 0; k < L.n; k++) {
+        const int64_t nz = L.size[k][0], ny = L.size[k][1], nx = L.size[k][2];
+        if (nz <= 0 || ny <= 0 || nx <= 0) continue;
+        const int64_t src0 = offset + L.src[k][0] * g.s[0] + L.src[k][1] * g.s[1] + L.src[k][2];
+        const int64_t dst0 = offset + L.dst[k][0] * g.s[0] + L.dst[k][1] * g.s[1] + L.dst[k][2];
+        bool vec = nx % 4 == 0 && strides_ok && buf_ok && L.start[k] % 4 == 0;
+        if (dir != COPY_UNPACK) vec = vec && src0 % 4 == 0;
+        if (dir != COPY_PACK) vec = vec && dst0 % 4 == 0;
+        const int64_t upr = vec ? nx / 4 : nx;
+        if (upr * ny >= kMaxUnits) return hipErrorInvalidValue;   // a plane of one box beyond 2^30 units
+        // split along z so that each piece stays below 2^30 units
+        const int64_t zstep = std::max<int64_t>(1, kMaxUnits / (upr * ny));
+        for (int64_t z0 = 0; z0 < nz; z0 += zstep) {
+            const int64_t zn = std::min(zstep, nz - z0);
+            if (P.n == kCopyBoxes) {
+                const hipError_t e = launch(P);
+                if (e != hipSuccess) return e;
+                P = CopyPlan{};
+            }
+            CopyBox& B = P.box[P.n];
+            B.src = src0 + z0 * g.s[0];
+            B.dst = dst0 + z0 * g.s[0];
+            B.buf = L.start[k] + z0 * ny * nx;
+            B.nx = (uint32_t)nx;
+            B.ny = (uint32_t)ny;
+            B.upr = (uint32_t)upr;
+            B.units = (uint32_t)(upr * ny * zn);
+            B.vec = vec ? 1u : 0u;
+            B.by_row = fast_div(B.upr);
+            B.by_y = fast_div(B.ny);
+            P.bstart[P.n + 1] = P.bstart[P.n] + (B.units + 255u) / 256u;
+            P.n++;
+        }
+    }
+    return launch(P);
 }
 
 hipError_t launch_boxcopy(int dtype, int dir, void* field, const Grid3& g, int64_t offset, const CopyList& L,
