@@ -120,7 +120,7 @@ hipError_t launch_program(const ProgView& v, hipStream_t s);
 // source text, compilation (shared by equal programs), launch on the
 // current device (loads the code object there once)
 struct RtcProgram;
-std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms);
+std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight);
 std::shared_ptr<RtcProgram> program_compile(const std::string& src, std::string& log);
 hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s);
 

@@ -50,12 +50,14 @@ std::string gname(int off) { return off < 0 ? "gm" + std::to_string(-off) : "g" 
 
 }  // namespace
 
-std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms) {
-    const int ns = 2 * rz + 2, ldy = kProgTileY + 2 * ry, plane4 = ldy * GX;
+std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight) {
+    // tight: a ring of 2 rz + 1 planes (less LDS, so more workgroups per CU)
+    // whose refill waits for a second barrier after the compute
+    const int ns = 2 * rz + (tight ? 1 : 2), ldy = kProgTileY + 2 * ry, plane4 = ldy * GX;
     const int ngroups = plane4, nload = (ngroups + kProgThreads - 1) / kProgThreads;
     std::ostringstream s;
     s << "// generated stencil program: " << nin << " inputs, " << nout << " outputs, " << terms.size()
-      << " terms, reach z " << rz << " y " << ry << "\n";
+      << " terms, reach z " << rz << " y " << ry << (tight ? ", tight ring" : "") << "\n";
     s << "typedef float f4 __attribute__((ext_vector_type(4)));\n"
          "__device__ __forceinline__ f4 fma4(f4 a, f4 b, f4 c) {\n"
          "  return (f4){__builtin_fmaf(a.x, b.x, c.x), __builtin_fmaf(a.y, b.y, c.y),\n"
@@ -178,6 +180,7 @@ std::string program_source(int nin, int nout, int rz, int ry, const std::vector<
                 s << "          if (x0 + " << i << " < nx) out" << o << "[oo + " << i << "] = acc" << o << "[" << i
                   << "];\n";
         s << "        }\n      }\n";
+        if (tight) s << "      __syncthreads();\n";
         s << "      if (more) {\n";
         lput((j + 2 * rz + 1) % ns, "        ");
         s << "      }\n      __syncthreads();\n    }\n";

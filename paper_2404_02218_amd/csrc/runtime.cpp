@@ -250,6 +250,7 @@ struct stencil_plan_s {
     int nin = 0, nout = 0, reach[3] = {0, 0, 0};
     std::vector<ProgTerm> pterms;
     std::shared_ptr<RtcProgram> rtc;   // the compiled program (variant 0)
+    std::shared_ptr<RtcProgram> rtc_tight;   // with the tight LDS ring (variant 2, compiled on first use)
 
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -284,7 +285,7 @@ bool tb_batch_supported(const stencil_plan_s* p) {
 }
 
 int variant_count_of(const stencil_plan_s* p) {
-    if (p->program) return 2;
+    if (p->program) return 3;
     if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
     if (p->ndim != 3) return 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
@@ -1104,7 +1105,7 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
         return st;
     }
     std::string log;
-    p->rtc = program_compile(program_source(nin, nout, reach[0], reach[1], pt), log);
+    p->rtc = program_compile(program_source(nin, nout, reach[0], reach[1], pt, false), log);
     if (!p->rtc) {
         delete p;
         return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
@@ -1140,7 +1141,13 @@ stencil_status stencil_program_apply(stencil_plan p, void* const* outs, const vo
     v.nty = (L.g.n[1] + kProgTileY - 1) / kProgTileY;
     chunking(L.g.n[0], 64, v.zc, v.nzc);
     if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) return STENCIL_OK;
+    if (p->variant == 2 && !p->rtc_tight) {
+        std::string log;
+        p->rtc_tight = program_compile(program_source(p->nin, p->nout, p->reach[0], p->reach[1], p->pterms, true), log);
+        if (!p->rtc_tight) return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
+    }
     if (p->variant == 0) HIP_TRY(launch_program_rtc(*p->rtc, v, (hipStream_t)stream));
+    else if (p->variant == 2) HIP_TRY(launch_program_rtc(*p->rtc_tight, v, (hipStream_t)stream));
     else HIP_TRY(launch_program(v, (hipStream_t)stream));
     return STENCIL_OK;
 }
@@ -1793,7 +1800,7 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
     const std::string tile = std::to_string(kProgTileX) + "x" + std::to_string(kProgTileY) + "_t" +
                              std::to_string(kProgThreads);
     if (p->program) {
-        name = (variant == 0 ? "program_rtc_" : "program_interp_") + tile;
+        name = (variant == 0 ? "program_rtc_" : variant == 1 ? "program_interp_" : "program_rtc_tight_") + tile;
     } else if (variant == 0) {
         name = "point";
     } else if (variant_of(variant).tb) {

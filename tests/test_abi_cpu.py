@@ -272,8 +272,9 @@ def test_program_variants_and_compiled_kernel_limits():
                    for _ in range(int(rng.integers(1, 3)))]) for _ in range(64)]
         terms[0] = (0, 1.0, [(3, (2,) * ndim), (2, (-2,) * ndim)])
         p = _program(shape=(7, 9, 11)[3 - ndim:], halo=2, nin=4, nout=4, terms=terms)
-        assert p.variant_count() == 2
-        assert [p.variant_name(v) for v in range(2)] == ["program_rtc_64x16_t256", "program_interp_64x16_t256"]
+        assert p.variant_count() == 3
+        assert [p.variant_name(v) for v in range(3)] == ["program_rtc_64x16_t256", "program_interp_64x16_t256",
+                                                         "program_rtc_tight_64x16_t256"]
         assert p.variant == 0
         p.variant = 1
         assert p.variant == 1
