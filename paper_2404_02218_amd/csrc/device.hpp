@@ -56,14 +56,20 @@ struct Storage<float> {
 };
 
 // bf16: widening is exact (the 16 bits are the top half of an FP32); narrowing
-// rounds to nearest, ties to even, by adding 0x7FFF plus the lowest kept bit
-// before truncation; NaN stays a quiet NaN.
+// is gfx950's conversion (v_cvt_pk_bf16_f32: round to nearest, ties to even; a
+// NaN stays a quiet NaN), two values per instruction where they are stored
+// together.  The FP32 value is pinned in a register first, as for f16 below,
+// so that no kernel folds the narrowing into the producing operation.
 __device__ static inline float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 __device__ static inline uint16_t f_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    asm volatile("" : "+v"(f));
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+__device__ static inline uint32_t f2_to_bf16x2(float a, float b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const b2 r = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, r);
 }
 
 template <>
@@ -78,11 +84,12 @@ struct Storage<bf16> {
     }
     __device__ static inline void store4(bf16* p, float4 v) {
         uint2 r;
-        r.x = (uint32_t)f_to_bf16(v.x) | ((uint32_t)f_to_bf16(v.y) << 16);
-        r.y = (uint32_t)f_to_bf16(v.z) | ((uint32_t)f_to_bf16(v.w) << 16);
+        r.x = f2_to_bf16x2(v.x, v.y);
+        r.y = f2_to_bf16x2(v.z, v.w);
         *reinterpret_cast<uint2*>(p) = r;
     }
     __device__ static inline void store(bf16* p, float v) { p->bits = f_to_bf16(v); }
+    __device__ static inline uint32_t pack2(float a, float b) { return f2_to_bf16x2(a, b); }
     // eight consecutive elements (16 bytes) as two float4
     __device__ static inline void load8(const bf16* p, float4& a, float4& b, bool nt) {
         typedef uint32_t u4v __attribute__((ext_vector_type(4)));
@@ -95,10 +102,10 @@ struct Storage<bf16> {
     __device__ static inline void store8(bf16* p, float4 a, float4 b, bool nt) {
         typedef uint32_t u4v __attribute__((ext_vector_type(4)));
         u4v r;
-        r.x = (uint32_t)f_to_bf16(a.x) | ((uint32_t)f_to_bf16(a.y) << 16);
-        r.y = (uint32_t)f_to_bf16(a.z) | ((uint32_t)f_to_bf16(a.w) << 16);
-        r.z = (uint32_t)f_to_bf16(b.x) | ((uint32_t)f_to_bf16(b.y) << 16);
-        r.w = (uint32_t)f_to_bf16(b.z) | ((uint32_t)f_to_bf16(b.w) << 16);
+        r.x = f2_to_bf16x2(a.x, a.y);
+        r.y = f2_to_bf16x2(a.z, a.w);
+        r.z = f2_to_bf16x2(b.x, b.y);
+        r.w = f2_to_bf16x2(b.z, b.w);
         if (nt)
             __builtin_nontemporal_store(r, reinterpret_cast<u4v*>(p));
         else
@@ -111,8 +118,8 @@ struct Storage<bf16> {
     }
     __device__ static inline void store4_nt(bf16* p, float4 v) {
         u2v r;
-        r.x = (uint32_t)f_to_bf16(v.x) | ((uint32_t)f_to_bf16(v.y) << 16);
-        r.y = (uint32_t)f_to_bf16(v.z) | ((uint32_t)f_to_bf16(v.w) << 16);
+        r.x = f2_to_bf16x2(v.x, v.y);
+        r.y = f2_to_bf16x2(v.z, v.w);
         __builtin_nontemporal_store(r, reinterpret_cast<u2v*>(p));
     }
 };
@@ -146,6 +153,9 @@ struct Storage<f16> {
         *reinterpret_cast<h4*>(p) = r;
     }
     __device__ static inline void store(f16* p, float v) { *p = f_to_f16(v); }
+    __device__ static inline uint32_t pack2(float a, float b) {
+        return (uint32_t)__builtin_bit_cast(uint16_t, f_to_f16(a)) | ((uint32_t)__builtin_bit_cast(uint16_t, f_to_f16(b)) << 16);
+    }
     __device__ static inline void load8(const f16* p, float4& a, float4& b, bool nt) {
         typedef _Float16 h8 __attribute__((ext_vector_type(8)));
         const h8 r = nt ? __builtin_nontemporal_load(reinterpret_cast<const h8*>(p)) : *reinterpret_cast<const h8*>(p);

@@ -192,20 +192,16 @@ __device__ __forceinline__ void tb2_store(__amdgpu_buffer_rsrc_t r, uint32_t vof
                 if (x0 + i < nx) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[i]), r, voff + 4 * i, soff, kStoreNT);
         }
     } else {
-        uint16_t h[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const T t = Storage<T>::from_f(o[i]);
-            h[i] = __builtin_bit_cast(uint16_t, t);
-        }
         if (full) {
             typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-            const u2 v = {(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
+            const u2 v = {Storage<T>::pack2(o[0], o[1]), Storage<T>::pack2(o[2], o[3])};
             __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, kStoreNT);
         } else {
 #pragma unroll
             for (int i = 0; i < 4; i++)
-                if (x0 + i < nx) __builtin_amdgcn_raw_buffer_store_b16(h[i], r, voff + 2 * i, soff, kStoreNT);
+                if (x0 + i < nx)
+                    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, Storage<T>::from_f(o[i])), r,
+                                                          voff + 2 * i, soff, kStoreNT);
         }
     }
 }
