@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (else tune)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage dtype of the headline leg (profiling of the 16-bit kernels)")
+    ap.add_argument("--leg", default=None,
+                    choices=["pw", "pw_loop", "slab", "faces", "absorbing", "heat2d", "batch", "adjoint"],
+                    help="run one secondary leg only and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (for counter scaling)")
     return ap.parse_args()
@@ -611,6 +614,17 @@ def main():
         sys.exit(1)
     n, nsteps = args.n, args.nsteps
     pts = float(n) ** 3 * nsteps
+    if args.leg:
+        legs = {"pw": lambda: bench_pw(S, W, max(1, args.steps)),
+                "pw_loop": lambda: bench_pw_loop(S, W, max(1, args.steps)),
+                "slab": lambda: bench_slab_share(S, W, max(1, args.steps)),
+                "faces": lambda: bench_faces(S, W),
+                "absorbing": lambda: bench_absorbing(S, W, max(1, args.steps)),
+                "heat2d": lambda: bench_heat2d(S, W, max(1, args.steps)),
+                "batch": lambda: bench_batch(S, W, max(1, args.steps)),
+                "adjoint": lambda: bench_adjoint(S, W, max(1, args.steps))}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return
     if args.only_heat:
         out = {"heat3d_so4": bench_heat3d(S, W, args.steps, args.variant, args.heat_steps)}
         if args.copy_calibration:
