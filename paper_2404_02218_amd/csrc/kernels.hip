@@ -87,7 +87,10 @@ __global__ void k_inject(T* base, SrcList src, int arow) {
     const int b = src.gbeg[g], e = src.gbeg[g + 1];
     T* p = base + src.off[src.grp[b]];
     float v = Storage<T>::load(p);
-    for (int k = b; k < e; k++) v = inject<T>(v, src_amount(src, arow, src.grp[k]));
+    for (int k = b; k < e; k++) {
+        const int s = src.grp[k];
+        v = inject<T>(v, src.amp[(int64_t)arow * src.n + s] * (src.scale ? src.scale[s] : 1.0));
+    }
     Storage<T>::store(p, v);
 }
 
@@ -302,6 +305,24 @@ __global__ void k_gather(const double* trace8, const double* w, int nc, int64_t 
     double acc = 0.0;
     for (int c = 0; c < nc; c++) acc = fma(w[r * nc + c], v[c], acc);
     trace[i] = acc;
+}
+
+// interpolated sources: amp8[t][e] = w[e] * amp[t][e >> shift] (FP64), the
+// amount of corner entry e of source e >> shift
+__global__ void k_spread(const double* amp, const double* w, int shift, int64_t n8, int64_t rows, double* amp8) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * n8) return;
+    const int64_t t = i / n8, e = i - t * n8;
+    amp8[i] = w[e] * amp[t * (n8 >> shift) + (e >> shift)];
+}
+
+hipError_t launch_spread(const double* amp, const double* w, int shift, int64_t n8, int64_t rows, double* amp8,
+                         hipStream_t s) {
+    if (n8 == 0 || rows == 0) return hipSuccess;
+    const int64_t total = n8 * rows;
+    hipLaunchKernelGGL(k_spread, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, amp, w, shift, n8, rows,
+                       amp8);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather(const double* trace8, const double* w, int nc, int64_t n, int64_t rows, double* trace,

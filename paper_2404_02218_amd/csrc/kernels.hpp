@@ -37,19 +37,12 @@ struct SrcList {
     const int* zyx4;
     const int* tile_begin;
     const int64_t* off;
-    const double* amp;    // [rows][n >> col_shift]; row chosen per launch
+    const double* amp;    // [rows][n]; row chosen per launch
     const double* scale;  // [n] multiplier of amp, or null
-    int col_shift;        // entry i takes amplitude column i >> col_shift
     int ngrp;             // distinct positions
     const int* grp;       // entries ordered by (offset, index)
     const int* gbeg;      // [ngrp + 1] CSR of grp by position
 };
-
-// the FP64 amount entry `idx` adds at amplitude row `row`
-__device__ static inline double src_amount(const SrcList& s, int row, int idx) {
-    const double a = s.amp[(int64_t)row * (s.n >> s.col_shift) + (idx >> s.col_shift)];
-    return s.scale ? a * s.scale[idx] : a;
-}
 
 struct RecList {
     int n;
@@ -202,6 +195,8 @@ inline constexpr int kTB2ZChunks[] = {256, 128, 64};
 inline constexpr int kNumTB2ZChunks = sizeof(kTB2ZChunks) / sizeof(kTB2ZChunks[0]);
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s);
 hipError_t launch_gather(const double* trace8, const double* w, int nc, int64_t n, int64_t rows, double* trace,
+                         hipStream_t s);
+hipError_t launch_spread(const double* amp, const double* w, int shift, int64_t n8, int64_t rows, double* amp8,
                          hipStream_t s);
 hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecList& rec, int trow,
                          hipStream_t s);

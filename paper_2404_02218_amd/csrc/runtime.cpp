@@ -204,8 +204,6 @@ struct PointTables {
     DevTable grp, gbeg;           // entries grouped by position (point-kernel injection)
     int n = 0, ngrp = 0;
     int cfg = -1;
-    int col_shift = 0;            // interpolated sources: entry i uses amplitude column i >> col_shift
-    const double* wscale = nullptr;   // and is scaled by wscale[i]
 };
 
 struct stencil_plan_s {
@@ -221,15 +219,13 @@ struct stencil_plan_s {
     PointTables src, rec, adjrec;
     PointTables src_ext;   // sources listed under every tile within R of them (temporal blocking)
     DevBuf tb_pair[2];     // the second field pair of the temporally blocked sweep (zero halos)
-    // interpolated sources and receivers (stencil_run_interp): corner weights,
-    // the corner trace, and the source mapping applied by prepare_points
+    // interpolated sources and receivers (stencil_run_interp): corner
+    // weights, the corners' amplitudes and the corner trace
     DevTable interp_sw, interp_rw;
+    DevBuf interp_amp, interp_trace;
     // absorbing layer (stencil_wave_damping): FP32 profiles [n0 | n1 | n2]
     DevTable damp;
     bool damped = false;
-    DevBuf interp_trace;
-    int interp_shift = 0;
-    const double* interp_w = nullptr;
     DevTable periodic_dummy;
     // graph cache of stencil_run
     hipStream_t cap = nullptr;
@@ -346,8 +342,6 @@ void zyx_of(const Layout& L, const int64_t* p3, int out[3]) {
 // point under every tile whose box widened by `ext` in x and y holds it.
 stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T, int ext = 0) {
     T.n = (int)n;
-    T.col_shift = 0;
-    T.wscale = nullptr;
     std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; i++) off[i] = interior_offset(L, pos + 3 * i);
     ST_TRY(T.off.upload(off.data(), sizeof(int64_t) * (size_t)n));
@@ -407,8 +401,7 @@ SrcList src_list(const PointTables& T, const double* amp, const double* scale) {
     s.tile_begin = (const int*)T.tiles.buf.p;
     s.off = (const int64_t*)T.off.buf.p;
     s.amp = amp;
-    s.scale = scale ? scale : T.wscale;
-    s.col_shift = T.col_shift;
+    s.scale = scale;
     s.ngrp = T.ngrp;
     s.grp = (const int*)T.grp.buf.p;
     s.gbeg = (const int*)T.gbeg.buf.p;
@@ -819,10 +812,6 @@ static stencil_status prepare_points(stencil_plan p, const stencil_source* src, 
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, cfg, p->src));
     if (var.tb) ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src_ext, 4));
     ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
-    for (PointTables* T : {&p->src, &p->src_ext}) {
-        T->col_shift = p->interp_shift;
-        T->wscale = p->interp_w;
-    }
     return STENCIL_OK;
 }
 
@@ -866,8 +855,6 @@ static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, 
                                     (int64_t)(uintptr_t)p->tb_pair[1].p,
                                     p->src.n,
                                     p->rec.n,
-                                    (int64_t)(uintptr_t)p->src.wscale,
-                                    p->src.col_shift,
                                     (int64_t)(uintptr_t)p->src.grp.buf.p,
                                     (int64_t)(uintptr_t)p->src.gbeg.buf.p,
                                     (int64_t)p->damped,
@@ -933,8 +920,6 @@ stencil_status stencil_wave_damping(stencil_plan p, const double* profile) {
 stencil_status stencil_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream) {
     ST_TRY(check_sweep_plan(p));
-    p->interp_shift = 0;
-    p->interp_w = nullptr;
     return run_common(p, fields, nsteps, src, rec, stream);
 }
 
@@ -1002,15 +987,16 @@ stencil_status stencil_run_interp(stencil_plan p, void** fields, int64_t nsteps,
     if (nr > 0 && nsteps * nr * nc > (int64_t(1) << 31)) return fail(STENCIL_E_NOMEM, "corner trace too large");
     ST_TRY(p->interp_sw.upload(sw.data(), sizeof(double) * sw.size()));
     ST_TRY(p->interp_rw.upload(rw.data(), sizeof(double) * rw.size()));
+    if (ns > 0 && nsteps * ns * nc > (int64_t(1) << 31)) return fail(STENCIL_E_NOMEM, "corner amplitudes too large");
     ST_TRY(p->interp_trace.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nsteps * nr * nc)));
-    const stencil_source s8{ns * nc, sp.data(), ns ? src->amp : nullptr};
+    ST_TRY(p->interp_amp.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nsteps * ns * nc)));
+    // each corner entry's amount, w * amp (FP64), for the ordinary point-source path
+    if (ns > 0)
+        HIP_TRY(launch_spread(src->amp, (const double*)p->interp_sw.buf.p, nd, ns * nc, nsteps,
+                              (double*)p->interp_amp.p, (hipStream_t)stream));
+    const stencil_source s8{ns * nc, sp.data(), (const double*)p->interp_amp.p};
     const stencil_receivers r8{nr * nc, rp.data(), (double*)p->interp_trace.p};
-    p->interp_shift = ns ? nd : 0;
-    p->interp_w = ns ? (const double*)p->interp_sw.buf.p : nullptr;
-    const stencil_status st = run_common(p, fields, nsteps, ns ? &s8 : nullptr, nr ? &r8 : nullptr, stream);
-    p->interp_shift = 0;
-    p->interp_w = nullptr;
-    ST_TRY(st);
+    ST_TRY(run_common(p, fields, nsteps, ns ? &s8 : nullptr, nr ? &r8 : nullptr, stream));
     if (nr > 0)
         HIP_TRY(launch_gather((const double*)p->interp_trace.p, (const double*)p->interp_rw.buf.p, nc, nr, nsteps,
                               rec->trace, (hipStream_t)stream));

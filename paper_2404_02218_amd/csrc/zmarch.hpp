@@ -293,7 +293,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
                 const int dy = e[1] - Y0, dx = e[2] - X0;
                 const int idx = e[3];
-                const double amt = src_amount(v.src, arow, idx);
+                const double amt = v.src.amp[(int64_t)arow * v.src.n + idx] * (v.src.scale ? v.src.scale[idx] : 1.0);
 #pragma unroll
                 for (int j = 0; j < VY; j++)
 #pragma unroll

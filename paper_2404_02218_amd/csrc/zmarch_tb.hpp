@@ -369,7 +369,7 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
                 const int* e = v.src_e.zyx4 + 4 * e_next;
                 e_next++;
                 e_z = e_next < e_end ? v.src_e.zyx4[4 * e_next] : INT_MAX;
-                const double amt = src_amount(v.src_e, arow, e[3]);
+                const double amt = v.src_e.amp[(int64_t)arow * v.src_e.n + e[3]];
 #pragma unroll
                 for (int i = 0; i < 4; i++)
                     if (e[1] == y0 && e[2] == x0 + i) o[i] = inject<T>(o[i], amt);
@@ -400,7 +400,7 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
                     const int* e = v.src_t.zyx4 + 4 * t_next;
                     t_next++;
                     t_z = t_next < t_end ? v.src_t.zyx4[4 * t_next] : INT_MAX;
-                    const double amt = src_amount(v.src_t, arow + 1, e[3]);
+                    const double amt = v.src_t.amp[(int64_t)(arow + 1) * v.src_t.n + e[3]];
 #pragma unroll
                     for (int i = 0; i < 4; i++)
                         if (e[1] == y0 && e[2] == x0 + i) o2[i] = inject<T>(o2[i], amt);
