@@ -162,10 +162,10 @@ stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, con
  * is a host array of extent_0 + ... + extent_{ndim-1} doubles (the per-axis
  * profiles one after another in axis order), g at a point = the sum of its
  * coordinates' entries (added first axis first, in FP32).  Sources are added
- * after the damped update as before.  NULL removes the layer.  The plan then
- * runs the z-marching and point kernels only (no temporally blocked
- * variants; a selected one reverts to the default), and the adjoint path
- * refuses it.  Errors: STENCIL_E_STATE for heat plans,
+ * after the damped update as before.  NULL removes the layer.  Every variant
+ * of the plan takes the layer (the temporally blocked one in both of its
+ * stages) and they agree bit for bit; the adjoint path refuses a damped
+ * plan.  Errors: STENCIL_E_STATE for heat plans,
  * STENCIL_E_UNSUPPORTED for 16-bit storage, STENCIL_E_INVALID for negative
  * or non-finite entries. */
 stencil_status stencil_wave_damping(stencil_plan plan, const double* profile);

@@ -269,6 +269,7 @@ hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& 
 hipError_t launch_tb2(int mode, int radius, int dtype, const TBView& v, const Coefs& w, int arow, int trow_u,
                       int trow_p, hipStream_t s) {
     if (mode == MODE_WAVE && radius == 4) return tb2_wave(dtype, v, w, arow, trow_u, trow_p, s);
+    if (mode == MODE_WAVE_DAMP && radius == 4 && dtype == DT_F32) return tb2_wave_damp_f32(v, w, arow, trow_u, trow_p, s);
     if (mode == MODE_HEAT && dtype == DT_F32) return tb2_heat_f32(radius, v, w, s);
     return hipErrorInvalidValue;
 }

@@ -82,6 +82,7 @@ struct TBView {
     SrcList src_t;
     SrcList src_e;
     RecList rec;
+    const float* damp;  // MODE_WAVE_DAMP: per-axis damping [n0 | n1 | n2]
     uint32_t range;   // bytes of each field's allocation (< 2^31)
 };
 
@@ -186,6 +187,7 @@ hipError_t launch_tb2(int mode, int radius, int dtype, const TBView& v, const Co
                       int trow_p, hipStream_t s);
 hipError_t tb2_wave(int dtype, const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
 hipError_t tb2_heat_f32(int radius, const TBView& v, const Coefs& w, hipStream_t s);
+hipError_t tb2_wave_damp_f32(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s);
 // batched shots: d_views[nshots] (device), d_block_map as for launch_zmarch_batch
 hipError_t tb2_batch(int dtype, const TBView* d_views, const int* d_block_map, int nblocks, const Coefs& w, int arow,
                      int trow_u, int trow_p, hipStream_t s);

@@ -267,7 +267,7 @@ stencil_status check_plan(stencil_plan p, bool want_batch) {
 // storage type) and the 3D heat (FP32), with the zero halo.  Its loads start
 // 8 elements left of a tile and address a field with 32-bit byte offsets.
 bool tb_supported(const stencil_plan_s* p) {
-    if (p->batch || p->ndim != 3 || p->bc != STENCIL_BC_DIRICHLET0 || p->damped) return false;
+    if (p->batch || p->ndim != 3 || p->bc != STENCIL_BC_DIRICHLET0) return false;
     const bool wave = p->kind == STENCIL_WAVE2 && p->radius == 4;
     const bool heat = p->kind == STENCIL_HEAT && p->dtype == STENCIL_F32;
     return (wave || heat) && p->L.g.xlead >= 8 && p->L.bytes < (int64_t(1) << 31);
@@ -545,6 +545,8 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
     const SrcList st = src_list(p->src, src ? src->amp : nullptr, nullptr);
     const SrcList se = src_list(p->src_ext, src ? src->amp : nullptr, nullptr);
     const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    const int mode = p->damped ? MODE_WAVE_DAMP : MODE_WAVE;
+    const float* damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
     int64_t passes = nsteps / 2;
     if (passes & 1) passes--;
     void* pairs[2][2] = {{a, b}, {p->tb_pair[0].p, p->tb_pair[1].p}};
@@ -565,10 +567,11 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
         v.src_t = st;
         v.src_e = se;
         v.rec = rl;
+        v.damp = damp;
         v.range = (uint32_t)L.bytes;
         const int tu = (rl.n > 0 && k >= 1) ? (int)(2 * k - 1) : -1;
         const int tp = (rl.n > 0 && k >= 1) ? (int)(2 * k - 2) : -1;
-        HIP_TRY(launch_tb2(MODE_WAVE, p->radius, p->dtype, v, p->w, (int)(2 * k), tu, tp, s));
+        HIP_TRY(launch_tb2(mode, p->radius, p->dtype, v, p->w, (int)(2 * k), tu, tp, s));
         newest = dst[0];
         prev = dst[1];
     }
@@ -587,8 +590,9 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
         set_tiling(v, L, plain);
         v.src = st;
         v.rec = rl;
+        v.damp = damp;
         const int trow = (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1;
-        HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, plain.cfg, v, p->w, (int)(t & 1), (int)t, trow, s));
+        HIP_TRY(launch_zmarch(mode, p->radius, p->dtype, plain.cfg, v, p->w, (int)(t & 1), (int)t, trow, s));
     }
     if (rl.n > 0 && nsteps > 0) HIP_TRY(launch_record(p->dtype, (nsteps & 1) ? b : a, L.g, rl, (int)(nsteps - 1), s));
     return STENCIL_OK;
@@ -912,7 +916,6 @@ stencil_status stencil_wave_damping(stencil_plan p, const double* profile) {
         base += (size_t)g.n[a];
     }
     ST_TRY(p->damp.upload(t.data(), sizeof(float) * std::max<size_t>(t.size(), 1)));
-    if (!p->damped && variant_of(p->variant).tb) p->variant = default_variant(p->L);
     p->damped = true;
     return STENCIL_OK;
 }
@@ -1941,6 +1944,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
                 t.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
                 chunking(L.g.n[0], var.zc, t.zc, t.nzc);
                 t.range = (uint32_t)L.bytes;
+                t.damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
                 return launch_tb2(mode, p->radius, p->dtype, t, p->w, 0, -1, -1, s);
             }
             if (p->batch)

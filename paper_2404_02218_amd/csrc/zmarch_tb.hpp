@@ -92,7 +92,7 @@ __device__ static inline void tb2_ring_group(int k, int& ex, int& ey) {
 // k = 1 .. R within an axis).
 template <int R, int MODE, class ZT>
 __device__ __forceinline__ void tb2_star(const Coefs& w, ZT&& zt, const float* L, int W, const float4& prev,
-                                         const float4& beta, float (&o)[4]) {
+                                         const float4& beta, const float4& gam, float (&o)[4]) {
     const float4 c = zt(R);
     float acc[4];
 #pragma unroll
@@ -126,7 +126,10 @@ __device__ __forceinline__ void tb2_star(const Coefs& w, ZT&& zt, const float* L
             p[k - 1] = xv[4 + i + k];
         }
         acc[i] = axis_sum<R>(acc[i], w, m, p);
-        o[i] = time_update<MODE>(acc[i], comp(c, i), comp(prev, i), comp(beta, i));
+        if constexpr (MODE == MODE_WAVE_DAMP)
+            o[i] = damped_update(acc[i], comp(c, i), comp(prev, i), comp(beta, i), comp(gam, i));
+        else
+            o[i] = time_update<MODE>(acc[i], comp(c, i), comp(prev, i), comp(beta, i));
     }
 }
 
@@ -210,7 +213,7 @@ __device__ __forceinline__ void tb2_store(__amdgpu_buffer_rsrc_t r, uint32_t vof
 template <int MODE, int R_, typename T>
 __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb, int arow, int trow_u, int trow_p,
                                          float* __restrict__ lds) {
-    constexpr bool WAVE = MODE == MODE_WAVE;
+    constexpr bool WAVE = MODE != MODE_HEAT, DAMP = MODE == MODE_WAVE_DAMP;
     using Z = TB2<R_, WAVE>;
     using S = Storage<T>;
     constexpr int R = Z::R, Q = Z::Q, TX = Z::TX, TY = Z::TY, NT = Z::NT;
@@ -314,6 +317,24 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         qx[j] = tile_role ? make_float4(0.f, 0.f, 0.f, 0.f) : ld(rU, z1b - R + j, am);
     }
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // absorbing layer: this group's row and column damping (clamped into the
+    // interior: values outside it only feed points that are set to 0)
+    float4 dgx = zero4;
+    float dgy = 0.f;
+    if constexpr (DAMP) {
+        const float* D = v.damp + v.g.n[0];
+        dgy = D[min(max(y0, 0), ny - 1)];
+        dgx = make_float4(D[ny + min(max(x0, 0), nx - 1)], D[ny + min(max(x0 + 1, 0), nx - 1)],
+                          D[ny + min(max(x0 + 2, 0), nx - 1)], D[ny + min(max(x0 + 3, 0), nx - 1)]);
+    }
+    auto gamma_at = [&](int z) -> float4 {
+        if constexpr (DAMP) {
+            const float g = v.damp[min(max(z, 0), nz - 1)] + dgy;
+            return make_float4(g + dgx.x, g + dgx.y, g + dgx.z, g + dgx.w);
+        } else {
+            return zero4;
+        }
+    };
     float4 cp = zero4, cb = zero4;
     if constexpr (WAVE) {
         cp = ld(rP, z1b, ag);
@@ -364,7 +385,7 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         {
             const bool zin = z1 >= 0 && z1 < nz;
             float o[4];
-            tb2_star<R, MODE>(w, za, L1 + l1, W1, cp, cb, o);
+            tb2_star<R, MODE>(w, za, L1 + l1, W1, cp, cb, gamma_at(z1), o);
             while (WAVE && e_z == z1) {
                 const int* e = v.src_e.zyx4 + 4 * e_next;
                 e_next++;
@@ -393,9 +414,10 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
                 const int sz2 = s2 + 1 == NS2 ? 0 : s2 + 1;   // slot of plane z1 - R
                 float o2[4];
                 if constexpr (WAVE)
-                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, za(0), BQ[sz2 * Z::NTILE + tid], o2);
+                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, za(0), BQ[sz2 * Z::NTILE + tid], gamma_at(z),
+                                      o2);
                 else
-                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, zero4, zero4, o2);
+                    tb2_star<R, MODE>(w, zb2, U2 + sz2 * P2 + l2, W2, zero4, zero4, zero4, o2);
                 while (WAVE && t_z == z) {
                     const int* e = v.src_t.zyx4 + 4 * t_next;
                     t_next++;
@@ -428,7 +450,7 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
 }
 
 template <int MODE, int R, typename T>
-__global__ __launch_bounds__(kTB2Threads, (TB2<R, MODE == MODE_WAVE>::WAVES_PER_SIMD)) void k_tb2(TBView v, Coefs w, int arow,
+__global__ __launch_bounds__(kTB2Threads, (TB2<R, MODE != MODE_HEAT>::WAVES_PER_SIMD)) void k_tb2(TBView v, Coefs w, int arow,
                                                                                                int trow_u, int trow_p) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     tb2_tile<MODE, R, T>(v, w, xcd_remap(blockIdx.x, gridDim.x), arow, trow_u, trow_p, lds);
@@ -461,7 +483,7 @@ static hipError_t tb2_batch_launch(const TBView* views, const int* bmap, int nbl
 
 template <int MODE, int R, typename T>
 static hipError_t tb2_launch(const TBView& v, const Coefs& w, int arow, int trow_u, int trow_p, hipStream_t s) {
-    constexpr size_t lds = sizeof(float) * TB2<R, MODE == MODE_WAVE>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(float) * TB2<R, MODE != MODE_HEAT>::LDS_FLOATS;
     const int64_t nb = (int64_t)v.ntx * v.nty * v.nzc;
     if (nb == 0) return hipSuccess;
     auto k = k_tb2<MODE, R, T>;
