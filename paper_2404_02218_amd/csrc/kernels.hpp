@@ -193,6 +193,15 @@ hipError_t tb2_batch(int dtype, const TBView* d_views, const int* d_block_map, i
                      int trow_u, int trow_p, hipStream_t s);
 // tile shape, threads and z-chunk lengths of the temporally blocked sweep
 inline constexpr int kTB2TileX = 64, kTB2TileY = 32, kTB2Threads = 768;
+// multi-step 2D heat (heat2d_tb.hip): T steps per launch on TX x TY tiles
+struct Heat2dCfg {
+    int t, tx, ty;
+};
+inline constexpr Heat2dCfg kHeat2dCfgs[] = {{4, 16, 16}, {8, 16, 16}, {8, 32, 32}, {16, 32, 32}};
+inline constexpr int kNumHeat2dCfgs = sizeof(kHeat2dCfgs) / sizeof(kHeat2dCfgs[0]);
+hipError_t launch_heat2d_tb(int cfg, int radius, const float* in, float* out, const Grid3& g, const Coefs& w,
+                            hipStream_t s);
+
 inline constexpr int kTB2ZChunks[] = {256, 128, 64};
 inline constexpr int kNumTB2ZChunks = sizeof(kTB2ZChunks) / sizeof(kTB2ZChunks[0]);
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s);

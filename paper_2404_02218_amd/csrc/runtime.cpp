@@ -280,10 +280,16 @@ bool tb_batch_supported(const stencil_plan_s* p) {
     return true;
 }
 
+// 2D heat, FP32, zero halo, radius <= 2: variants 1.. are the multi-step kernels
+bool heat2d_supported(const stencil_plan_s* p) {
+    return !p->batch && !p->program && p->ndim == 2 && p->kind == STENCIL_HEAT && p->dtype == STENCIL_F32 &&
+           p->bc == STENCIL_BC_DIRICHLET0 && p->radius <= 2;
+}
+
 int variant_count_of(const stencil_plan_s* p) {
     if (p->program) return 3;
     if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
-    if (p->ndim != 3) return 1;
+    if (p->ndim != 3) return heat2d_supported(p) ? 1 + kNumHeat2dCfgs : 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
 }
 
@@ -598,10 +604,43 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
     return STENCIL_OK;
 }
 
+// 2D heat with the multi-step kernel: an even number of T-step passes
+// between the two buffers (so, as after nsteps plain sweeps, the newest level
+// is in a when nsteps is even), then plain sweeps for the rest.
+static stencil_status enqueue_run_heat2d(stencil_plan p, void* a, void* b, int64_t nsteps, hipStream_t s) {
+    const Layout& L = p->L;
+    const int cfg = p->variant - 1;
+    const int T = kHeat2dCfgs[cfg].t;
+    int64_t passes = nsteps / T;
+    if (passes & 1) passes--;
+    void* cur = a;
+    void* nxt = b;
+    for (int64_t k = 0; k < passes; k++) {
+        HIP_TRY(launch_heat2d_tb(cfg, p->radius, (const float*)cur, (float*)nxt, L.g, p->w, s));
+        std::swap(cur, nxt);
+    }
+    Box3 box{};
+    for (int a3 = 0; a3 < 3; a3++) {
+        box.lo[a3] = 0;
+        box.n[a3] = L.g.n[a3];
+    }
+    for (int64_t t = passes * T; t < nsteps; t++) {
+        ZView v{};
+        v.u = cur;
+        v.prev = nxt;
+        v.out = nxt;
+        v.g = L.g;
+        HIP_TRY(launch_point(MODE_HEAT, p->radius, p->dtype, v, p->w, box, s));
+        std::swap(cur, nxt);
+    }
+    return STENCIL_OK;
+}
+
 // Enqueue nsteps sweeps of a single plan (no capture logic here).
 stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, int64_t nsteps,
                            const stencil_source* src, const stencil_receivers* rec, hipStream_t s) {
     const Layout& L = p->L;
+    if (p->ndim == 2 && p->variant > 0 && heat2d_supported(p)) return enqueue_run_heat2d(p, a, b, nsteps, s);
     Variant var = variant_of(p->variant);
     const bool wave = p->kind == STENCIL_WAVE2;
     if (var.tb && wave) return enqueue_run_tb(p, var, a, b, beta, nsteps, src, rec, s);
@@ -721,6 +760,7 @@ stencil_status stencil_create(stencil_plan* out, stencil_kind kind, int ndim, co
         return st;
     }
     p->variant = default_variant(p->L);
+    if (heat2d_supported(p)) p->variant = 2;   // 8 steps per launch on 16 x 16 tiles
     *out = p;
     return STENCIL_OK;
 }
@@ -1790,6 +1830,9 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
                              std::to_string(kProgThreads);
     if (p->program) {
         name = (variant == 0 ? "program_rtc_" : variant == 1 ? "program_interp_" : "program_rtc_tight_") + tile;
+    } else if (p->ndim == 2 && variant > 0) {
+        const Heat2dCfg& c = kHeat2dCfgs[variant - 1];
+        name = "tb2d_t" + std::to_string(c.t) + "_" + std::to_string(c.tx) + "x" + std::to_string(c.ty);
     } else if (variant == 0) {
         name = "point";
     } else if (variant_of(variant).tb) {
@@ -1928,7 +1971,11 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             }
             if (st != STENCIL_OK) break;
         }
+        const bool heat2d = p->ndim == 2 && var_i > 0;
         auto launch = [&]() -> hipError_t {
+            if (heat2d)
+                return launch_heat2d_tb(var_i - 1, p->radius, (const float*)views[0].u, (float*)views[0].out, p->L.g,
+                                        p->w, s);
             if (var.tb && p->batch)
                 return tb2_batch(p->dtype, (const TBView*)tvt.buf.p, (const int*)bs.buf.p, bst.back(), p->w, 0, -1, -1, s);
             if (var.tb) {
@@ -1976,6 +2023,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             break;
         }
         if (var.tb) ms *= 0.5f;   // one launch advances two steps
+        if (heat2d) ms /= (float)kHeat2dCfgs[var_i - 1].t;
         if (ms < best_ms) {
             best_ms = ms;
             best = var_i;

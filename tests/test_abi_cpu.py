@@ -135,8 +135,14 @@ def test_variants_are_listed():
     assert S.Plan(S.WAVE2, (64, 64, 64), 2, S.second_derivative_weights(4)).variant_count() == 17
     assert S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8),
                   bc=S.BC_PERIODIC).variant_count() == 17
+    # 2D heat (FP32, zero halo): the point kernel and four multi-step kernels
     p2 = S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2))
-    assert p2.variant_count() == 1 and p2.variant == 0
+    assert [p2.variant_name(v) for v in range(p2.variant_count())] == [
+        "point", "tb2d_t4_16x16", "tb2d_t8_16x16", "tb2d_t8_32x32", "tb2d_t16_32x32"]
+    assert p2.variant == 2
+    assert S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2), bc=S.BC_PERIODIC).variant_count() == 1
+    assert S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2), dtype=S.BF16).variant_count() == 1
+    assert S.Plan(S.WAVE2, (64, 64), 1, [-2.0, 1.0]).variant_count() == 1
     with pytest.raises(S.StencilError):
         p.variant = n
 
