@@ -387,11 +387,17 @@ stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfiel
 
 /* ------------------------------------------------------------ variants */
 
-/* Kernel variants of a plan (tile shape and z-chunk of the 3D sweep; variant
- * 0 is the one-thread-per-point kernel).  Every variant computes identical
- * bits.  stencil_tune times the candidates on the caller's fields (reading
- * them only; outputs go to a scratch field it allocates and frees) and keeps
- * the fastest; the choice is cached per (kind, ndim, radius, dtype, shape). */
+/* Kernel variants of a plan.  Variant 0 is the one-thread-per-point kernel.
+ * 3D plans add the z-marching sweep (tile shape and z-chunk), and for the
+ * radius-4 wave and the FP32 heat with the zero halo the depth-2 temporally
+ * blocked sweep (two steps per launch).  2D FP32 heat plans with the zero
+ * halo and radius <= 2 add multi-step kernels (T = 4, 8 or 16 steps per
+ * launch in LDS).  Program plans have their own three (see
+ * stencil_program_create).  Every variant of a plan computes identical bits.
+ * stencil_tune times the candidates on the caller's fields (reading them
+ * only; outputs go to a scratch field it allocates and frees) and keeps the
+ * fastest per step of one launch; the choice is cached per (kind, ndim,
+ * radius, dtype, damping, shape). */
 stencil_status stencil_variant_count(stencil_plan plan, int* count);
 stencil_status stencil_variant_name(stencil_plan plan, int variant, char* buf, size_t len);
 stencil_status stencil_get_variant(stencil_plan plan, int* variant);
