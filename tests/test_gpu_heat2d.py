@@ -39,3 +39,17 @@ def test_multistep_heat2d_workload_meets_oracle_tolerance(device):
     c = [H.alpha * x for x in oracle.fd_weights_float(2)]
     ref = W.interior_of(oracle.heat_run(W.embed(u0, 1), 1, 1, c, H.nsteps), 1)
     assert rel_err(got, ref) <= 1e-5
+
+
+def test_tuned_2d_heat_plan_equals_plain_sweeps(device):
+    """stencil_tune picks among the point kernel and the multi-step kernels;
+    whatever it picks, a run equals the point kernel's bits."""
+    shape = (96, 130)
+    u0 = W.round_to_storage(np.random.default_rng(5).uniform(0, 1, shape), "f32")
+    plan = S.Plan(S.HEAT, shape, 1, S.heat_weights(2, 0.2), halo=1)
+    f = [plan.field() for _ in range(2)]
+    f[0].load(W.embed(u0, 1))
+    plan.tune(f, reps=3)
+    assert 0 <= plan.variant < plan.variant_count()
+    got = gpu_heat(plan, u0, 37)
+    assert np.array_equal(got, gpu_heat(plan, u0, 37, variant=0))
