@@ -148,8 +148,11 @@ stencil_status stencil_apply(stencil_plan plan, void* out, const void* const* in
  * level (and, for the wave, fields[1] the one before).  With periodic
  * boundaries the halo of the current level is refreshed before each sweep by
  * a self-exchange (the dmp.swap of a one-rank periodic grid, Section 4.2).
- * src/rec may be NULL.  The launches of the run are captured into one HIP
- * graph per (pointers, nsteps) and replayed. */
+ * src/rec may be NULL.  The launches of a run of two or more steps are
+ * captured into one HIP graph per (pointers, nsteps, variant, tables) and
+ * replayed; with the environment variable STENCIL_NO_GRAPH set to a value
+ * other than 0 they are enqueued directly instead (the same kernels and
+ * bits). */
 stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream);
 
