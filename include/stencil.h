@@ -330,7 +330,10 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
  * exchange first where needed) and outputs' halos are untouched.  No output
  * may alias an input or another output.  Each term evaluates as
  * on its output's FP32 sum s in program order: s = fma(coeff, a, s) for
- * one factor, s = fma(fl(coeff * a), b, s) for two (fma: one rounding). */
+ * one factor, s = fma(fl(coeff * a), b, s) for two (fma: one rounding).
+ * The first apply of a compiled variant on a device loads its code object
+ * (hipModuleLoadData), which may synchronise the device: make that first
+ * call outside stream capture; later applies only enqueue the kernel. */
 stencil_status stencil_program_apply(stencil_plan plan, void* const* outs, const void* const* ins, void* stream);
 
 /* ------------------------------------------------------- exchange schedule */
