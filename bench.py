@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage dtype of the headline leg (profiling of the 16-bit kernels)")
     ap.add_argument("--leg", default=None,
-                    choices=["pw", "pw_loop", "slab", "faces", "absorbing", "heat2d", "batch", "adjoint"],
+                    choices=["pw", "pw_loop", "slab", "faces", "absorbing", "heat2d", "batch", "adjoint",
+                             "precision"],
                     help="run one secondary leg only and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (for counter scaling)")
@@ -426,6 +427,56 @@ def bench_absorbing(S, W, steps, n=512, width=40, gmax=0.1):
             "vs_undamped_same_variant": round(ms0 / ms, 3)}
 
 
+def bench_precision(S, W, n=512, nsteps=400, every=25):
+    """Error of the headline workload (so-8 wave, n^3, nsteps steps, Ricker at
+    the centre, zero start) against the FP64 oracle for FP32, BF16 and FP16
+    storage, the oracle fed the same storage-rounded velocity term.  Both
+    advance in segments of `every` steps; the error is max over the snapshots
+    (every `every` steps and the last) of |gpu - oracle|, over max over the
+    snapshots of |oracle| (a pointwise relative error is ill-posed at the
+    wavefield's zeros, and the final level alone is divided by an amplitude
+    that has decayed as the wave spread); the final level's own ratio is
+    reported beside it.  About 40 s of host time per storage type at 512^3."""
+    import torch
+
+    import oracle
+    P = W.wave3d_c3(n=n, nsteps=nsteps)
+    c = oracle.fd_weights_float(8)
+    out = {"interior": [n] * 3, "steps": nsteps, "snapshot_every": every,
+           "metric": "max over snapshots |gpu - oracle| / max over snapshots |oracle|"}
+    for dn in ("f32", "bf16", "f16"):
+        plan = S.Plan(S.WAVE2, P.shape, 4, S.second_derivative_weights(8), halo=4, dtype=S.DTYPES[dn])
+        f = [plan.field() for _ in range(3)]
+        beta = W.round_to_storage(P.beta, dn)
+        f[2].load(W.embed(beta, 4))
+        bb = W.embed(beta, 4)
+        a = np.zeros(tuple(s + 8 for s in P.shape))
+        b = np.zeros_like(a)
+        num = den = 0.0
+        secs = 0.0
+        for t0 in range(0, nsteps, every):
+            k = min(every, nsteps - t0)
+            amp = P.src_amp[t0:t0 + k]
+            plan.run(f, k, src=P.src, src_amp=torch.from_numpy(np.ascontiguousarray(amp)).cuda())
+            torch.cuda.synchronize()
+            got = f[0].interior(4)
+            t = time.perf_counter()
+            a, b, _ = oracle.wave_run(a, b, bb, 4, 4, c, k, src=P.src, src_amp=amp)
+            secs += time.perf_counter() - t
+            ref = W.interior_of(a, 4)
+            d = float(np.max(np.abs(got - ref)))
+            m = float(np.max(np.abs(ref)))
+            num, den = max(num, d), max(den, m)
+        final = d / m
+        log(f"[bench] precision {dn}: {num / den:.3e} over snapshots, final level {final:.3e} "
+            f"(oracle {secs:.1f} s)")
+        out[dn] = {"error": num / den, "final_level_error": final, "variant": plan.variant_name(plan.variant),
+                   "oracle_s": round(secs, 1)}
+        del f, a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_heat2d(S, W, steps):
     """2D 5-point heat, 256^2, Dirichlet zero halo, 100 steps: a field of
     260 KiB stays in L2, so launches, not HBM bandwidth, set the time.  The
@@ -637,7 +688,8 @@ def main():
                 "absorbing": lambda: bench_absorbing(S, W, max(1, args.steps)),
                 "heat2d": lambda: bench_heat2d(S, W, max(1, args.steps)),
                 "batch": lambda: bench_batch(S, W, max(1, args.steps)),
-                "adjoint": lambda: bench_adjoint(S, W, max(1, args.steps))}
+                "adjoint": lambda: bench_adjoint(S, W, max(1, args.steps)),
+                "precision": lambda: bench_precision(S, W)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
     if args.only_heat:
