@@ -1877,6 +1877,57 @@ static std::string tune_key(stencil_plan p) {
     return k;
 }
 
+// A 2D heat run is launch-bound: time 16 steps of variant `var` the way a run
+// executes them, as a captured graph replayed `reps` times (eager launches
+// leave larger gaps between kernels and would favour the deepest variants).
+// The steps read `in` once and then alternate between the two scratch fields.
+static stencil_status time_heat2d_graph(stencil_plan p, int var, const void* in, void* s0, void* s1, int reps,
+                                        hipStream_t s, hipEvent_t e0, hipEvent_t e1, float& ms_per_step) {
+    constexpr int kSteps = 16;
+    if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    const int T = var == 0 ? 1 : kHeat2dCfgs[var - 1].t;
+    Box3 box{};
+    for (int a = 0; a < 3; a++) {
+        box.lo[a] = 0;
+        box.n[a] = p->L.g.n[a];
+    }
+    HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    const void* src = in;
+    void* dst = s0;
+    for (int k = 0; k < kSteps / T && e == hipSuccess; k++) {
+        if (var == 0) {
+            ZView v{};
+            v.u = src;
+            v.prev = dst;
+            v.out = dst;
+            v.g = p->L.g;
+            e = launch_point(MODE_HEAT, p->radius, p->dtype, v, p->w, box, p->cap);
+        } else {
+            e = launch_heat2d_tb(var - 1, p->radius, (const float*)src, (float*)dst, p->L.g, p->w, p->cap);
+        }
+        src = dst;
+        dst = dst == s0 ? s1 : s0;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap, &graph);
+    if (e == hipSuccess) e = ec;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipGraphLaunch(ex, s);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; r++) e = hipGraphLaunch(ex, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("tuning graph: ") + hipGetErrorString(e));
+    ms_per_step = ms / (float)(reps * kSteps);
+    return STENCIL_OK;
+}
+
 stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void* stream) {
     if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
     if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
@@ -1920,6 +1971,16 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     stencil_status st = STENCIL_OK;
     DevTable vt, bs, tvt;
     for (int var_i = p->batch ? 1 : 0; var_i < nvar && st == STENCIL_OK; var_i++) {
+        if (heat2d_supported(p)) {
+            float ms = 0;
+            st = time_heat2d_graph(p, var_i, fields[0], scratch, (char*)scratch + round_up(p->L.bytes, 256), reps, s,
+                                   e0, e1, ms);
+            if (st == STENCIL_OK && ms < best_ms) {
+                best_ms = ms;
+                best = var_i;
+            }
+            continue;
+        }
         const Variant var = variant_of(var_i);
         std::vector<ZView> views;
         std::vector<int> bst(1, 0);
