@@ -251,7 +251,12 @@ hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s) 
             e = hipModuleLoadData(&rp.mod[dev], rp.code.data());
             if (e != hipSuccess) return e;
             e = hipModuleGetFunction(&rp.fn[dev], rp.mod[dev], "stencil_program");
-            if (e != hipSuccess) return e;
+            if (e != hipSuccess) {
+                (void)hipModuleUnload(rp.mod[dev]);
+                rp.mod[dev] = nullptr;
+                rp.fn[dev] = nullptr;
+                return e;
+            }
         }
         fn = rp.fn[dev];
     }
