@@ -4,6 +4,8 @@ oracle finishes in seconds, so these check what holds at any size:
   * one sweep from random levels (plus a source) over the whole 512^3 field
     against the oracle's one-step update computed everywhere;
   * the exact light cone after many steps from a zero start;
+  * the 512^3 x 50-step heat in its tuned variant against the whole oracle
+    run (the 13-point heat is cheap enough for the oracle at full size);
   * batched == sequential (bitwise) for the 32 uneven shots;
   * the 256^3 x 500-step checkpointed gradient against central differences of
     the GPU misfit, with observed data from the FP64 oracle, and the traces
@@ -14,7 +16,7 @@ import pytest
 import oracle
 import paper_2404_02218_amd as S
 import workloads as W
-from _helpers import rel_err, torch_f64
+from _helpers import gpu_heat, rel_err, torch_f64
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +95,30 @@ def test_c3_full_size_multi_step_matches_oracle_on_a_slab(device):
     a, _, _ = oracle.wave_run(z, z, b, 4, 4, oracle.fd_weights_float(8), steps, src=src, src_amp=amp)
     err = rel_err(got, W.interior_of(a, 4))
     print(f"{steps} steps at 512^3 vs oracle on z < 256: {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_c2_full_size_tuned_run_matches_oracle(device):
+    """The 512^3 so-4 heat, 50 steps, in the variant the tuner picks (the
+    configuration the benchmark times), against the whole FP64 oracle run;
+    the tuned run also gives the plain sweep's bits."""
+    import torch
+    P = W.heat3d_c2()
+    u0 = W.round_to_storage(P.u0, "f32")
+    plan = S.Plan(S.HEAT, P.shape, 2, S.heat_weights(4, P.alpha), halo=2)
+    f = [plan.field() for _ in range(2)]
+    f[0].load(W.embed(u0, 2))
+    plan.tune(f, reps=2)
+    tuned = plan.variant_name(plan.variant)
+    got = gpu_heat(plan, u0, P.nsteps)
+    plain = gpu_heat(plan, u0, P.nsteps, variant=2)
+    assert np.array_equal(got, plain), tuned
+    del f, plain
+    torch.cuda.empty_cache()
+    c = [P.alpha * x for x in oracle.fd_weights_float(4)]
+    ref = W.interior_of(oracle.heat_run(W.embed(u0, 2), 2, 2, c, P.nsteps), 2)
+    err = rel_err(got, ref)
+    print(f"C2 512^3 x {P.nsteps}, {tuned}: {err:.2e}")
     assert err <= 1e-5
 
 
