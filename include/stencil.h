@@ -29,6 +29,11 @@
  *     The library only enqueues work on the caller's stream (a hipStream_t
  *     passed as void*; NULL = the legacy default stream); STENCIL_OK means
  *     "enqueued", not "finished".
+ *   - The library uses whichever HIP runtime (libamdhip64) the process has
+ *     loaded when it is loaded, and pointers and streams must come from that
+ *     same runtime.  A host program that brings its own copy of the runtime
+ *     (PyTorch does) loads that copy first; a second runtime in one process
+ *     reports no device.
  *   - Arrays of shapes, coordinates and exchange declarations are host
  *     memory, C order (slowest axis first), and only the first ndim slots of
  *     a [3] array are read.

@@ -94,6 +94,12 @@ def lib():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
             "or `python paper_2404_02218_amd/build.py`; there is no CPU fallback")
+    # torch ships its own HIP runtime.  Loaded first, it is the one the
+    # library's HIP dependency binds to, so device pointers and streams from
+    # torch are valid here; loaded after the library, a second runtime would
+    # come up beside the system one, and whichever initialises second finds
+    # no device.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
     st = C.c_int

@@ -45,6 +45,25 @@ def _create(kind=S.WAVE2, shape=(8, 9, 10), radius=4, halo=4, dtype=S.F32, bc=S.
     return st, h
 
 
+
+def test_library_loads_into_the_hip_runtime_torch_uses():
+    """Loading the library from a fresh process, before anything imported
+    torch, leaves exactly one HIP runtime in the process: torch's, which the
+    device pointers and streams come from."""
+    import subprocess
+    import sys
+    code = ("import json, paper_2404_02218_amd._abi as A; A.lib(); "
+            "print(json.dumps(sorted({l.split()[-1] for l in open('/proc/self/maps') "
+            "if 'libamdhip64' in l or 'libhsa-runtime64' in l})))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = json.loads(out.stdout.strip().splitlines()[-1])
+    assert sum("libamdhip64" in x for x in libs) == 1, libs
+    assert sum("libhsa-runtime64" in x for x in libs) == 1, libs
+    import torch
+    assert all(x.startswith(os.path.dirname(torch.__file__)) for x in libs), libs
+
 @pytest.mark.parametrize("kw,status", [
     (dict(radius=5, halo=5), -2),
     (dict(radius=0), -2),
