@@ -407,8 +407,9 @@ stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfiel
  * stencil_program_create).  Every variant of a plan computes identical bits.
  * stencil_tune times the candidates on the caller's fields (reading them
  * only; outputs go to a scratch field it allocates and frees) and keeps the
- * fastest per step of one launch; the choice is cached per (kind, ndim,
- * radius, dtype, damping, shape). */
+ * fastest per step of one launch (2D multi-step plans: per step of 96
+ * steps captured in a graph, as runs execute them); the choice is cached per
+ * (kind, ndim, radius, dtype, damping, shape). */
 stencil_status stencil_variant_count(stencil_plan plan, int* count);
 stencil_status stencil_variant_name(stencil_plan plan, int variant, char* buf, size_t len);
 stencil_status stencil_get_variant(stencil_plan plan, int* variant);

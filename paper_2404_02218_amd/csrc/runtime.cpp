@@ -1877,13 +1877,15 @@ static std::string tune_key(stencil_plan p) {
     return k;
 }
 
-// A 2D heat run is launch-bound: time 16 steps of variant `var` the way a run
-// executes them, as a captured graph replayed `reps` times (eager launches
+// A 2D heat run is launch-bound: time 96 steps of variant `var` the way a run
+// executes them, as a captured graph replayed at least 10 times (eager launches
 // leave larger gaps between kernels and would favour the deepest variants).
 // The steps read `in` once and then alternate between the two scratch fields.
 static stencil_status time_heat2d_graph(stencil_plan p, int var, const void* in, void* s0, void* s1, int reps,
                                         hipStream_t s, hipEvent_t e0, hipEvent_t e1, float& ms_per_step) {
-    constexpr int kSteps = 16;
+    // 96 steps: 6 to 96 launches, enough that the per-replay cost of a graph
+    // launch does not decide between depths
+    constexpr int kSteps = 96;
     if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
     const int T = var == 0 ? 1 : kHeat2dCfgs[var - 1].t;
     Box3 box{};
@@ -1917,14 +1919,15 @@ static stencil_status time_heat2d_graph(stencil_plan p, int var, const void* in,
     if (graph) (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(ex, s);   // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; r++) e = hipGraphLaunch(ex, s);
+    const int nrep = std::max(reps, 10);
+    for (int r = 0; r < nrep && e == hipSuccess; r++) e = hipGraphLaunch(ex, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (ex) (void)hipGraphExecDestroy(ex);
     if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("tuning graph: ") + hipGetErrorString(e));
-    ms_per_step = ms / (float)(reps * kSteps);
+    ms_per_step = ms / (float)(nrep * kSteps);
     return STENCIL_OK;
 }
 
