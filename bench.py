@@ -280,11 +280,12 @@ def bench_heat3d(S, W, steps, variant=-1, nsteps=50):
             "effective_GBps_plain_sweep_bytes": round(hg * 8, 1)}
 
 
-def bench_pw(S, W, steps, n=512):
+def bench_pw(S, W, steps, n=512, variant=-1):
     """The flux-form C-grid advection of (u, v, w) as a 60-term stencil
     program (3 inputs, 3 outputs, diagonal offsets), 512^3 interior (the
     134M-point size of the paper's PW advection runs), random velocity,
-    zero halo.  One program apply per step."""
+    zero halo.  One program apply per step; `variant` >= 0 times that variant
+    alone (profiling), else every compiled one."""
     import torch
     from paper_2404_02218_amd.program import Program, pw_advection_terms
     shape = (n, n, n)
@@ -294,17 +295,26 @@ def bench_pw(S, W, steps, n=512):
     for f in ins:
         f.view[1:-1, 1:-1, 1:-1] = torch.rand(shape, generator=gen, device="cuda") - 0.5
     outs = [prog.field() for _ in range(3)]
-    prog.apply_program(outs, ins)
-    with Timer() as t:
-        for _ in range(steps):
-            prog.apply_program(outs, ins)
-    ms = t.ms / steps
+    # the compiled forms (the generic kernel, variant 1, is a cross-check):
+    # 64 x 16 tiles, the tight ring, 64 x 32 tiles; the fastest is reported
+    per_variant = {}
+    for v in [variant] if variant >= 0 else [x for x in (0, 2, 3) if x < prog.variant_count()]:
+        prog.variant = v
+        prog.apply_program(outs, ins)
+        with Timer() as t:
+            for _ in range(steps):
+                prog.apply_program(outs, ins)
+        per_variant[v] = t.ms / steps
+    prog.variant = min(per_variant, key=per_variant.get)
+    ms = per_variant[prog.variant]
     pts = float(n) ** 3
     gbs = 24.0 * pts / (ms * 1e-3) / 1e9
-    log(f"[bench] pw advection {n}^3: {ms:.3f} ms, {pts / (ms * 1e-3) / 1e9:.1f} GPts/s")
+    log(f"[bench] pw advection {n}^3: {ms:.3f} ms, {pts / (ms * 1e-3) / 1e9:.1f} GPts/s, {prog.variant_name(prog.variant)}"
+        f" (" + ", ".join(f"{prog.variant_name(v)} {m:.3f} ms" for v, m in per_variant.items()) + ")")
     return {"interior": list(shape), "terms": len(prog.terms), "GPts_s": round(pts / (ms * 1e-3) / 1e9, 2),
             "ms_per_apply": round(ms, 3), "algorithmic_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
             "bytes_per_point": 24, "variant": prog.variant_name(prog.variant),
+            "ms_per_variant": {prog.variant_name(v): round(m, 3) for v, m in per_variant.items()},
             "kernel": "stencil_program (compiled with the 60 terms as constants)"}
 
 
@@ -681,7 +691,7 @@ def main():
     n, nsteps = args.n, args.nsteps
     pts = float(n) ** 3 * nsteps
     if args.leg:
-        legs = {"pw": lambda: bench_pw(S, W, max(1, args.steps)),
+        legs = {"pw": lambda: bench_pw(S, W, max(1, args.steps), variant=args.variant),
                 "pw_loop": lambda: bench_pw_loop(S, W, max(1, args.steps)),
                 "slab": lambda: bench_slab_share(S, W, max(1, args.steps)),
                 "faces": lambda: bench_faces(S, W),

@@ -321,8 +321,12 @@ typedef struct {
  * (the message holds the compiler's log).  The plan compiles a kernel in
  * which the terms are constants (hiprtc, gfx950; plans with the same program
  * share it, and it is loaded on a device at the first apply there);
- * stencil_variant_count reports 2: variant 0 runs that kernel, variant 1 a
- * generic kernel that reads the terms at run time, with identical bits.
+ * stencil_variant_count reports 3 or 4 variants, all with identical bits:
+ * 0 runs that kernel on 64 x 16 tiles (256 threads); 1 a generic kernel
+ * that reads the terms at run time; 2 the compiled kernel with a plane ring
+ * one slot shorter (less LDS, a second barrier per plane); 3, where its LDS
+ * ring fits a compute unit (160 KiB), the compiled kernel on 64 x 32 tiles
+ * (512 threads).  Variants 2 and 3 are compiled at their first apply.
  * stencil_layout, stencil_exchanges(_box), stencil_halo_pack and _unpack,
  * the variant calls and stencil_destroy accept the plan; stencil_tune
  * refuses it. */

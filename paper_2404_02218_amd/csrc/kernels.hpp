@@ -114,8 +114,15 @@ hipError_t launch_program(const ProgView& v, hipStream_t s);
 // source text, compilation (shared by equal programs), launch on the
 // current device (loads the code object there once)
 struct RtcProgram;
-std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight);
-std::shared_ptr<RtcProgram> program_compile(const std::string& src, std::string& log);
+// tile_y: 16 (256 threads) or 32 (512 threads); the tile is 64 points wide
+std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight,
+                           int tile_y);
+// LDS bytes of the compiled kernel's plane ring
+inline size_t program_rtc_lds_bytes(int nin, int rz, int ry, bool tight, int tile_y) {
+    return 16 * (size_t)nin * (2 * rz + (tight ? 1 : 2)) * (tile_y + 2 * ry) * ((kProgTileX + 8) / 4);
+}
+inline constexpr size_t kLdsPerCu = 160 * 1024;
+std::shared_ptr<RtcProgram> program_compile(const std::string& src, int threads, std::string& log);
 hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s);
 
 // Tile shapes of the z-marching kernel: BX threads along x with VX points

@@ -6,7 +6,8 @@
 // (Section 4): the generic kernel in program.hip interprets the same terms.
 //
 // The generated kernel keeps that kernel's tiling (64 x 16 tiles, 256 threads,
-// 4 x points per thread, an LDS ring of 2 rz + 2 planes per input) and its
+// 4 x points per thread, an LDS ring of 2 rz + 2 planes per input; a taller
+// form has 64 x 32 tiles of 512 threads, half the halo rows per point) and its
 // arithmetic (terms in program order, one rounding per product and a fused
 // multiply-add into the output), so the two agree bit for bit.  What the
 // constants buy: the z loop is unrolled by the ring size, so every LDS read is
@@ -50,19 +51,23 @@ std::string gname(int off) { return off < 0 ? "gm" + std::to_string(-off) : "g" 
 
 }  // namespace
 
-std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight) {
+std::string program_source(int nin, int nout, int rz, int ry, const std::vector<ProgTerm>& terms, bool tight,
+                           int tile_y) {
     // tight: a ring of 2 rz + 1 planes (less LDS, so more workgroups per CU)
     // whose refill waits for a second barrier after the compute
-    const int ns = 2 * rz + (tight ? 1 : 2), ldy = kProgTileY + 2 * ry, plane4 = ldy * GX;
-    const int ngroups = plane4, nload = (ngroups + kProgThreads - 1) / kProgThreads;
+    // tile_y rows of 16 threads, each thread 4 consecutive x points of one row
+    const int threads = 16 * tile_y;
+    const int ns = 2 * rz + (tight ? 1 : 2), ldy = tile_y + 2 * ry, plane4 = ldy * GX;
+    const int ngroups = plane4, nload = (ngroups + threads - 1) / threads;
     std::ostringstream s;
     s << "// generated stencil program: " << nin << " inputs, " << nout << " outputs, " << terms.size()
-      << " terms, reach z " << rz << " y " << ry << (tight ? ", tight ring" : "") << "\n";
+      << " terms, reach z " << rz << " y " << ry << (tight ? ", tight ring" : "") << ", tile 64x" << tile_y
+      << "\n";
     s << "typedef float f4 __attribute__((ext_vector_type(4)));\n"
          "__device__ __forceinline__ f4 fma4(f4 a, f4 b, f4 c) {\n"
          "  return (f4){__builtin_fmaf(a.x, b.x, c.x), __builtin_fmaf(a.y, b.y, c.y),\n"
          "              __builtin_fmaf(a.z, b.z, c.z), __builtin_fmaf(a.w, b.w, c.w)};\n}\n";
-    s << "extern \"C\" __global__ void __launch_bounds__(" << kProgThreads << ") stencil_program(";
+    s << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") stencil_program(";
     for (int f = 0; f < nin; f++) s << "const float* __restrict__ in" << f << ", ";
     for (int o = 0; o < nout; o++) s << "float* __restrict__ out" << o << ", ";
     s << "long long origin, long long sz, long long sy, int nx, int ny, int nz, int xmax4, int ntx, int nty, "
@@ -75,14 +80,14 @@ std::string program_source(int nin, int nout, int rz, int ry, const std::vector<
          "  const int tid = (int)threadIdx.x, tx = tid & 15, ty = tid >> 4;\n"
          "  const int tile_x = lb % ntx, tile_y = (lb / ntx) % nty, zch = lb / (ntx * nty);\n"
          "  const int X0 = tile_x * "
-      << kProgTileX << ", Y0 = tile_y * " << kProgTileY
+      << kProgTileX << ", Y0 = tile_y * " << tile_y
       << ";\n"
          "  const int zb = zch * zc, ze = min(zb + zc, nz);\n";
     // the groups this thread loads: LDS group gi = row * GX + column; rows and
     // planes clamp into the halo, columns to the row's last full group
     for (int k = 0; k < nload; k++) {
-        const bool always = (k + 1) * kProgThreads <= ngroups;
-        s << "  const int gi" << k << " = tid + " << k * kProgThreads << ";\n";
+        const bool always = (k + 1) * threads <= ngroups;
+        s << "  const int gi" << k << " = tid + " << k * threads << ";\n";
         s << "  const bool ok" << k << " = " << (always ? "true" : "gi" + std::to_string(k) + " < " + std::to_string(ngroups))
           << ";\n";
         s << "  const long long go" << k << " = origin + (long long)min(max(Y0 - " << ry << " + gi" << k << " / " << GX
@@ -192,6 +197,7 @@ std::string program_source(int nin, int nout, int rz, int ry, const std::vector<
 // ------------------------------------------------------------ compilation
 struct RtcProgram {
     std::vector<char> code;
+    int threads = 0;   // workgroup size
     std::mutex mu;
     hipModule_t mod[kMaxDevices] = {};
     hipFunction_t fn[kMaxDevices] = {};
@@ -202,7 +208,7 @@ std::mutex g_rtc_mu;
 std::map<std::string, std::shared_ptr<RtcProgram>> g_rtc;  // by source text
 }  // namespace
 
-std::shared_ptr<RtcProgram> program_compile(const std::string& src, std::string& log) {
+std::shared_ptr<RtcProgram> program_compile(const std::string& src, int threads, std::string& log) {
     {
         std::lock_guard<std::mutex> lk(g_rtc_mu);
         auto it = g_rtc.find(src);
@@ -225,6 +231,7 @@ std::shared_ptr<RtcProgram> program_compile(const std::string& src, std::string&
         size_t cs = 0;
         hiprtcGetCodeSize(prog, &cs);
         out = std::make_shared<RtcProgram>();
+        out->threads = threads;
         out->code.resize(cs);
         hiprtcGetCode(prog, out->code.data());
     }
@@ -277,7 +284,7 @@ hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s) 
     }
     void* rest[] = {&origin, &sz, &sy, &nx, &ny, &nz, &xmax4, &ntx, &nty, &zc};
     for (void* a : rest) args[na++] = a;
-    return hipModuleLaunchKernel(fn, (unsigned)nb, 1, 1, kProgThreads, 1, 1, 0, s, args, nullptr);
+    return hipModuleLaunchKernel(fn, (unsigned)nb, 1, 1, (unsigned)rp.threads, 1, 1, 0, s, args, nullptr);
 }
 
 }  // namespace stn

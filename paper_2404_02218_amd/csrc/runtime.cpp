@@ -247,6 +247,7 @@ struct stencil_plan_s {
     std::vector<ProgTerm> pterms;
     std::shared_ptr<RtcProgram> rtc;   // the compiled program (variant 0)
     std::shared_ptr<RtcProgram> rtc_tight;   // with the tight LDS ring (variant 2, compiled on first use)
+    std::shared_ptr<RtcProgram> rtc_tall;    // 64 x 32 tiles of 512 threads (variant 3, compiled on first use)
 
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -287,7 +288,8 @@ bool heat2d_supported(const stencil_plan_s* p) {
 }
 
 int variant_count_of(const stencil_plan_s* p) {
-    if (p->program) return 3;
+    if (p->program)
+        return 3 + (program_rtc_lds_bytes(p->nin, p->reach[0], p->reach[1], false, 2 * kProgTileY) <= kLdsPerCu);
     if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
     if (p->ndim != 3) return heat2d_supported(p) ? 1 + kNumHeat2dCfgs : 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
@@ -1134,7 +1136,7 @@ stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t
         return st;
     }
     std::string log;
-    p->rtc = program_compile(program_source(nin, nout, reach[0], reach[1], pt, false), log);
+    p->rtc = program_compile(program_source(nin, nout, reach[0], reach[1], pt, false, kProgTileY), kProgThreads, log);
     if (!p->rtc) {
         delete p;
         return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
@@ -1166,17 +1168,20 @@ stencil_status stencil_program_apply(stencil_plan p, void* const* outs, const vo
     for (size_t t = 0; t < p->pterms.size(); t++) v.t[t] = p->pterms[t];
     v.rz = p->reach[0];
     v.ry = p->reach[1];
+    const int ty = p->variant == 3 ? 2 * kProgTileY : kProgTileY;
     v.ntx = (L.g.n[2] + kProgTileX - 1) / kProgTileX;
-    v.nty = (L.g.n[1] + kProgTileY - 1) / kProgTileY;
+    v.nty = (L.g.n[1] + ty - 1) / ty;
     chunking(L.g.n[0], 64, v.zc, v.nzc);
     if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) return STENCIL_OK;
-    if (p->variant == 2 && !p->rtc_tight) {
+    std::shared_ptr<RtcProgram>* lazy = p->variant == 2 ? &p->rtc_tight : p->variant == 3 ? &p->rtc_tall : nullptr;
+    if (lazy && !*lazy) {
         std::string log;
-        p->rtc_tight = program_compile(program_source(p->nin, p->nout, p->reach[0], p->reach[1], p->pterms, true), log);
-        if (!p->rtc_tight) return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
+        *lazy = program_compile(program_source(p->nin, p->nout, p->reach[0], p->reach[1], p->pterms, p->variant == 2, ty),
+                                16 * ty, log);
+        if (!*lazy) return fail(STENCIL_E_DEVICE, "compiling the stencil program failed: " + log);
     }
     if (p->variant == 0) HIP_TRY(launch_program_rtc(*p->rtc, v, (hipStream_t)stream));
-    else if (p->variant == 2) HIP_TRY(launch_program_rtc(*p->rtc_tight, v, (hipStream_t)stream));
+    else if (lazy) HIP_TRY(launch_program_rtc(**lazy, v, (hipStream_t)stream));
     else HIP_TRY(launch_program(v, (hipStream_t)stream));
     return STENCIL_OK;
 }
@@ -1829,7 +1834,10 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
     const std::string tile = std::to_string(kProgTileX) + "x" + std::to_string(kProgTileY) + "_t" +
                              std::to_string(kProgThreads);
     if (p->program) {
-        name = (variant == 0 ? "program_rtc_" : variant == 1 ? "program_interp_" : "program_rtc_tight_") + tile;
+        name = variant == 3 ? "program_rtc_" + std::to_string(kProgTileX) + "x" + std::to_string(2 * kProgTileY) + "_t" +
+                                  std::to_string(32 * kProgTileY)
+                            : (variant == 0 ? "program_rtc_" : variant == 1 ? "program_interp_" : "program_rtc_tight_") +
+                                  tile;
     } else if (p->ndim == 2 && variant > 0) {
         const Heat2dCfg& c = kHeat2dCfgs[variant - 1];
         name = "tb2d_t" + std::to_string(c.t) + "_" + std::to_string(c.tx) + "x" + std::to_string(c.ty);
