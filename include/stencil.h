@@ -328,8 +328,8 @@ typedef struct {
  * ring fits a compute unit (160 KiB), the compiled kernel on 64 x 32 tiles
  * (512 threads).  Variants 2 and 3 are compiled at their first apply.
  * stencil_layout, stencil_exchanges(_box), stencil_halo_pack and _unpack,
- * the variant calls and stencil_destroy accept the plan; stencil_tune
- * refuses it. */
+ * the variant calls, stencil_tune (fields = inputs, then outputs) and
+ * stencil_destroy accept the plan. */
 stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t* shape, int halo, int nin,
                                       int nout, const stencil_term* terms, int nterms, stencil_dtype dtype);
 
@@ -413,7 +413,11 @@ stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfiel
  * only; outputs go to a scratch field it allocates and frees) and keeps the
  * fastest per step of one launch (2D multi-step plans: per step of 96
  * steps captured in a graph, as runs execute them); the choice is cached per
- * (kind, ndim, radius, dtype, damping, shape). */
+ * (kind, ndim, radius, dtype, damping, shape).  For a program plan `fields`
+ * holds its nin input pointers, then its nout output pointers: the compiled
+ * variants (0, 2 and 3 where it exists) are applied to them, the fastest
+ * is kept, and the outputs hold the program's result (not cached; the
+ * first apply of each variant compiles and loads it, outside capture). */
 stencil_status stencil_variant_count(stencil_plan plan, int* count);
 stencil_status stencil_variant_name(stencil_plan plan, int variant, char* buf, size_t len);
 stencil_status stencil_get_variant(stencil_plan plan, int* variant);

@@ -1939,11 +1939,59 @@ static stencil_status time_heat2d_graph(stencil_plan p, int var, const void* in,
     return STENCIL_OK;
 }
 
+// Program plans: fields = the nin inputs, then the nout outputs.  Each
+// compiled variant (0, 2 and, where it exists, 3) is applied once untimed
+// (that compiles and loads it) and then `reps` times on the caller's fields;
+// the fastest is kept.  The outputs receive the program's result.
+static stencil_status tune_program(stencil_plan p, void* const* fields, int reps, void* stream) {
+    const void* ins[kProgMaxFields];
+    void* outs[kProgMaxFields];
+    for (int f = 0; f < p->nin; f++) ins[f] = fields[f];
+    for (int o = 0; o < p->nout; o++) outs[o] = fields[p->nin + o];
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(STENCIL_E_DEVICE, "hipEventCreate failed");
+    }
+    const int keep = p->variant, n = variant_count_of(p);
+    int best = keep;
+    float best_ms = 1e30f;
+    stencil_status st = STENCIL_OK;
+    for (int v : {0, 2, 3}) {
+        if (v >= n) continue;
+        p->variant = v;
+        st = stencil_program_apply(p, outs, ins, stream);
+        if (st != STENCIL_OK) break;
+        hipError_t e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess && st == STENCIL_OK; r++) st = stencil_program_apply(p, outs, ins, stream);
+        if (st != STENCIL_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(STENCIL_E_DEVICE, std::string("tuning a program: ") + hipGetErrorString(e));
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->variant = st == STENCIL_OK ? best : keep;
+    return st;
+}
+
 stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void* stream) {
     if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
     if (!fields) return fail(STENCIL_E_INVALID, "fields is NULL");
     if (reps < 1 || reps > 1000) return fail(STENCIL_E_INVALID, "reps must be 1..1000");
-    if (p->program) return fail(STENCIL_E_STATE, "stencil_tune takes sweep plans, not stencil programs");
+    if (p->program) return tune_program(p, fields, reps, stream);
     int nvar = 0;
     ST_TRY(stencil_variant_count(p, &nvar));
     const std::string key = tune_key(p);

@@ -290,8 +290,8 @@ def test_program_variants_and_compiled_kernel_limits():
     """Programs compile (hiprtc, gfx950) at creation: the largest one the
     limits allow (4 inputs and outputs, reach 2 on every axis, 64 terms: the
     most LDS) and 1D/2D ones.  The 64 x 32 compiled form is offered only where
-    its LDS ring fits a compute unit (not for the 3D one here), and
-    stencil_tune refuses program plans."""
+    its LDS ring fits a compute unit (not for the 3D one here).  stencil_tune
+    takes program plans; its argument checks come before any device call."""
     rng = np.random.default_rng(5)
     for ndim in (1, 2, 3):
         terms = [(int(rng.integers(0, 4)), float(rng.standard_normal()),
@@ -311,8 +311,9 @@ def test_program_variants_and_compiled_kernel_limits():
         p.variant = 1
         assert p.variant == 1
     lib = _abi.lib()
-    fake = (C.c_void_p * 3)(256, 512, 768)
-    assert lib.stencil_tune(p.handle, fake, 1, None) == -5
+    fake = (C.c_void_p * 8)(*[256 * (k + 1) for k in range(8)])
+    assert lib.stencil_tune(p.handle, fake, 0, None) == -1
+    assert lib.stencil_tune(p.handle, None, 1, None) == -1
 
 
 @pytest.mark.parametrize("shape", [(5, 6, 7), (4, 9), (11,), (1, 6, 5)])

@@ -101,6 +101,29 @@ def test_pw_advection_program_matches_the_oracle_scheme(device, shape):
         assert np.max(np.abs(rf[I])) > 0.1
 
 
+def test_tuning_a_program_keeps_a_compiled_variant_and_its_bits(device):
+    """stencil_tune on a program plan (fields: inputs, then outputs) times
+    the compiled variants on the caller's fields and keeps one of them; the
+    outputs then hold the program's result, the bits of every variant."""
+    shape = (20, 70, 130)
+    rng = np.random.default_rng(77)
+    vel = [W.round_to_storage(np.pad(rng.standard_normal(shape), 1, mode="wrap"), "f32") for _ in range(3)]
+    prog = Program(shape, 1, 3, 3, pw_advection_terms(1.0, 1.0, 1.0))
+    want = _run(prog, vel, variant=0)
+    ins = [prog.field() for _ in range(3)]
+    for f, a in zip(ins, vel):
+        f.load(a)
+    outs = [prog.field() for _ in range(3)]
+    v = prog.tune(ins + outs, reps=3)
+    assert v in (0, 2, 3) and v == prog.variant
+    import torch
+    torch.cuda.synchronize()
+    for o, w in zip(outs, want):
+        assert np.array_equal(o.to_numpy(), w)
+    for a, b in zip(_run(prog, vel, variant=v), want):
+        assert np.array_equal(a, b)
+
+
 def test_pw_advection_periodic_decomposition_equals_monolithic(device):
     """2 x 2 x 1 subdomains whose halos (faces, edges, corners) are filled by
     packing the neighbours' send boxes and unpacking them, on the GPU; the
