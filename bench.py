@@ -13,13 +13,16 @@ Also reported on the same GPU (`variants`):
   * the checkpointed misfit gradient (256^3, 500 steps, 64 receivers,
     checkpoints every 25 steps) against the plain forward of the same model.
 `cpu_baseline` times the FP64 oracle on the host cores on a bounded sample of
-the headline workload.
+the headline workload (and, labelled as such, on one thread for two steps).
+`runs` holds the median and minimum of the timed runs and the first run's
+time, which includes capturing the run's graph.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import hashlib
 import json
 import os
@@ -156,17 +159,35 @@ def wave_setup(S, W, n, nsteps, dtype, variant):
     return P, plan, f, amp
 
 
-def time_wave(plan, f, amp, P, steps, warmup):
+def time_wave(plan, f, amp, P, steps, warmup, per_run=None):
+    """Mean ms per run over `steps` timed runs (after `warmup` untimed ones).
+    per_run, if a dict, receives the first warm-up run's wall time (which
+    includes capturing and instantiating the run's graph) and the median and
+    minimum of the timed runs, each bracketed by its own events."""
+    import torch
+
     def one():
         f[0].storage.zero_()
         f[1].storage.zero_()
         plan.run(f, P.nsteps, src=P.src, src_amp=amp)
 
-    for _ in range(warmup):
+    for k in range(warmup):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         one()
+        torch.cuda.synchronize()
+        if k == 0 and per_run is not None:
+            per_run["first_run_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     with Timer() as t:
-        for _ in range(steps):
+        for k in range(steps):
+            ev[k].record()
             one()
+        ev[steps].record()
+    if per_run is not None:
+        runs = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+        per_run["median_ms"] = round(float(np.median(runs)), 3)
+        per_run["min_ms"] = round(runs[0], 3)
     return t.ms / steps
 
 
@@ -188,10 +209,42 @@ def cpu_baseline(W, n, budget_s=20.0):
     t0 = time.perf_counter()
     oracle.wave_run(z, z, beta, 4, 4, c, k, src=P.src, src_amp=P.src_amp)
     dt = time.perf_counter() - t0
-    return {"value": round(float(n) ** 3 * k / dt / 1e9, 4), "unit": "GPts/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle (C, OpenMP over z), so-8 wave {n}^3 interior, first {k} of the "
-                      f"400 leapfrog steps, {dt:.1f} s"}
+    out = {"value": round(float(n) ** 3 * k / dt / 1e9, 4), "unit": "GPts/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"FP64 oracle (C, OpenMP over z), so-8 wave {n}^3 interior, first {k} of the "
+                     f"400 leapfrog steps, {dt:.1f} s"}
+    # one thread, two steps (labelled as such), and the host it ran on
+    try:
+        gomp = C.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        P1 = W.wave3d_c3(n=n, nsteps=2)
+        t0 = time.perf_counter()
+        oracle.wave_run(z, z, beta, 4, 4, c, 2, src=P1.src, src_amp=P1.src_amp)
+        d1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": round(float(n) ** 3 * 2 / d1 / 1e9, 4), "unit": "GPts/s",
+                                "sample": f"the same oracle on one thread, first 2 steps, {d1:.1f} s"}
+    except OSError:
+        pass
+    out["host"] = host_cpu()
+    return out
+
+
+def host_cpu():
+    """CPU model and socket count from /proc/cpuinfo."""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key == "model name" and model is None:
+                    model = val.strip()
+                elif key == "physical id":
+                    sockets.add(val.strip())
+    except OSError:
+        pass
+    return {"model": model, "sockets": len(sockets) or None, "affinity_cores": len(os.sched_getaffinity(0))}
 
 
 def bench_batch(S, W, steps):
@@ -714,7 +767,8 @@ def main():
     es = 4 if args.storage == "f32" else 2
     vname = plan.variant_name(plan.variant)
     log(f"[bench] variant {vname}")
-    ms = time_wave(plan, f, amp, P, args.steps, args.warmup)
+    per_run = {}
+    ms = time_wave(plan, f, amp, P, args.steps, args.warmup, per_run)
     gpts = pts / (ms * 1e-3) / 1e9
     tb, launches, bpl, kname = launch_model(vname, nsteps, es, args.storage)
     kern_ms = ms / launches
@@ -728,6 +782,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.storage,
         "data": "synthetic",
+        "runs": dict(per_run, note="ms per step: median and min of the timed runs (each bracketed by "
+                                   "its own events); first_run_ms: the first warm-up run, which captures "
+                                   "and instantiates the run's graph"),
         "config": {"workload": f"wave3d_so8_{n}^3_{nsteps}steps", "interior": [n, n, n], "halo": 4,
                    "radius": 4, "leapfrog_steps": nsteps, "storage": args.storage, "variant": vname,
                    "source": "Ricker 10 Hz at the centre, layered velocity 1.5-4.5 km/s +-5%"},
