@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace stn {
 
 // ---------------------------------------------------------------- storage
@@ -212,6 +214,54 @@ __device__ static inline void store_vec(T* p, const float4 (&v)[VX / 4], bool nt
     } else {
         Storage<T>::store8(p, v[0], v[1], nt);
     }
+}
+
+// Loads that stay in flight across a compute phase are kept in the storage
+// type and widened to FP32 where they are consumed: a conversion placed next
+// to its load makes the wave wait for that load there.  RawGroup<T>::type
+// holds 4 consecutive elements as loaded.
+template <typename T>
+struct RawGroup {
+    typedef float4 type;
+};
+template <>
+struct RawGroup<bf16> {
+    typedef u2v type;
+};
+template <>
+struct RawGroup<f16> {
+    typedef u2v type;
+};
+
+// NT: the streaming (non-temporal) hint, fixed at compile time so that the
+// hint cannot be lost when the compiler merges the two forms of the load
+template <typename T, bool NT>
+__device__ static inline typename RawGroup<T>::type load4_raw(const T* p) {
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (NT) return Storage<float>::load4_nt(p);
+        else return Storage<float>::load4(p);
+    } else {
+        if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+        else return *reinterpret_cast<const u2v*>(p);
+    }
+}
+template <typename T>
+__device__ static inline float4 widen4(typename RawGroup<T>::type r) {
+    if constexpr (std::is_same<T, float>::value) {
+        return r;
+    } else if constexpr (std::is_same<T, bf16>::value) {
+        return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u), __uint_as_float(r.y << 16),
+                           __uint_as_float(r.y & 0xffff0000u));
+    } else {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 h = __builtin_bit_cast(h4, r);
+        return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+    }
+}
+template <typename T, int VX, bool NT>
+__device__ static inline void load_vec_raw(const T* p, typename RawGroup<T>::type (&r)[VX / 4]) {
+#pragma unroll
+    for (int c = 0; c < VX / 4; c++) r[c] = load4_raw<T, NT>(p + 4 * c);
 }
 
 // value after a round trip through the storage type

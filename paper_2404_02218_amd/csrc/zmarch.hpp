@@ -141,11 +141,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         for (int m = 0; m < NH; m++)
             if (hon[m]) *reinterpret_cast<float4*>(&L[hlds[m]]) = S::load4(U + (int64_t)p * sz + hoff[m]);
     }
-    float4 hal[NH];
+    // loads in flight across a plane's compute stay in the storage type
+    using Raw = typename RawGroup<T>::type;
+    Raw hal[NH];
     if (zb + R < ze) {
 #pragma unroll
         for (int m = 0; m < NH; m++)
-            if (hon[m]) hal[m] = S::load4(U + (int64_t)(zb + R) * sz + hoff[m]);
+            if (hon[m]) hal[m] = load4_raw<T, false>(U + (int64_t)(zb + R) * sz + hoff[m]);
     }
     float4 cp[VY][NV], cb[VY][NV];
     if constexpr (WAVE) {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // advances without register moves.  The plane loop below is unrolled
     // 2R+1 times so that every offset is a constant.
     constexpr int Q = 2 * R + 1;
-    float4 nq[VY][NV];   // the next leading plane, in flight during the compute
+    Raw nq[VY][NV];   // the next leading plane, in flight during the compute
     auto step = [&](auto off_c) {
         constexpr int OFF = decltype(off_c)::value;
         auto qi = [&](int k) -> float4(&)[VY][NV] { return q[(k + OFF) % Q]; };
@@ -195,25 +197,25 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             float* H = lds + hslot * PLANE;
 #pragma unroll
             for (int m = 0; m < NH; m++)
-                if (hon[m]) *reinterpret_cast<float4*>(&H[hlds[m]]) = hal[m];
+                if (hon[m]) *reinterpret_cast<float4*>(&H[hlds[m]]) = widen4<T>(hal[m]);
         }
 
         const bool more = z + 1 < ze;
-        float4 np[VY][NV], nb[VY][NV];
+        Raw np[VY][NV], nb[VY][NV];
         if (more) {
             const int64_t zn = (int64_t)(z + 1) * sz;
 #pragma unroll
-            for (int j = 0; j < VY; j++) load_vec<T, VX>(U + zn + (int64_t)R * sz + own[j], nq[j], false);
+            for (int j = 0; j < VY; j++) load_vec_raw<T, VX, false>(U + zn + (int64_t)R * sz + own[j], nq[j]);
             if (z + R + 1 < ze) {
 #pragma unroll
                 for (int m = 0; m < NH; m++)
-                    if (hon[m]) hal[m] = S::load4(U + zn + (int64_t)R * sz + hoff[m]);
+                    if (hon[m]) hal[m] = load4_raw<T, false>(U + zn + (int64_t)R * sz + hoff[m]);
             }
             if constexpr (WAVE) {
 #pragma unroll
                 for (int j = 0; j < VY; j++) {
-                    load_vec<T, VX>(P + zn + own[j], np[j], NTH);
-                    load_vec<T, VX>(B + zn + own[j], nb[j], NTH);
+                    load_vec_raw<T, VX, NTH>(P + zn + own[j], np[j]);
+                    load_vec_raw<T, VX, NTH>(B + zn + own[j], nb[j]);
                 }
             }
         }
@@ -367,10 +369,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             for (int j = 0; j < VY; j++)
 #pragma unroll
                 for (int c = 0; c < NV; c++) {
-                    q[OFF][j][c] = nq[j][c];
+                    q[OFF][j][c] = widen4<T>(nq[j][c]);
                     if constexpr (WAVE) {
-                        cp[j][c] = np[j][c];
-                        cb[j][c] = nb[j][c];
+                        cp[j][c] = widen4<T>(np[j][c]);
+                        cb[j][c] = widen4<T>(nb[j][c]);
                     }
                 }
         }
