@@ -176,6 +176,18 @@ __device__ __forceinline__ float4 tb2_bload4<f16>(__amdgpu_buffer_rsrc_t r, uint
     return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
 }
 
+// The same loads without widening (RawGroup), for loads that stay in flight
+// across a plane's compute: they are widened where the plane is consumed.
+template <typename T>
+__device__ __forceinline__ typename RawGroup<T>::type tb2_bload_raw(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                                     uint32_t soff) {
+    if constexpr (std::is_same<T, float>::value) {
+        return tb2_bload4<float>(r, off, soff);
+    } else {
+        return __builtin_bit_cast(u2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+    }
+}
+
 // Store a group of 4 points with the streaming hint at byte offset
 // voff + soff of the field behind `r`.  full: every point of the group is
 // interior (wave-uniform); otherwise points x0 + i >= nx are skipped.
@@ -262,6 +274,8 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
     const auto rU = rsrc(v.u), rO2 = rsrc(v.out2);
     const auto rP = WAVE ? rsrc(v.prev) : rU, rB = WAVE ? rsrc(v.beta) : rU, rO1 = WAVE ? rsrc(v.out1) : rO2;
     auto ld = [&](__amdgpu_buffer_rsrc_t r, int z, uint32_t off) -> float4 { return tb2_bload4<T>(r, off, soff(z)); };
+    using Raw = typename RawGroup<T>::type;
+    auto ldr = [&](__amdgpu_buffer_rsrc_t r, int z, uint32_t off) -> Raw { return tb2_bload_raw<T>(r, off, soff(z)); };
 
     // This thread's group of E (ex, ey): tile role (ex, ey) = (gx + 1, gy + R);
     // ring role: ring group k.  x0, y0: its first point.  Roles are per
@@ -369,14 +383,15 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         }
 
         const bool more = z1 + 1 < z1e;
-        float4 nq, np, nb, nm;
+        // the next plane's loads, in flight during the compute
+        Raw nq, np, nb, nm;
         if (more) {
-            nq = ld(rU, z1 + 1 + R, ag);
+            nq = ldr(rU, z1 + 1 + R, ag);
             if constexpr (WAVE) {
-                np = ld(rP, z1 + 1, ag);
-                nb = ld(rB, z1 + 1, ag);
+                np = ldr(rP, z1 + 1, ag);
+                nb = ldr(rB, z1 + 1, ag);
             }
-            if (!tile_role) nm = ld(rU, z1 + 1 + R, am);
+            if (!tile_role) nm = ldr(rU, z1 + 1 + R, am);
         }
         __syncthreads();
 
@@ -432,11 +447,11 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         }
 
         if (more) {
-            qa[OFF] = nq;
-            if (!tile_role) qx[OFF] = nm;
+            qa[OFF] = widen4<T>(nq);
+            if (!tile_role) qx[OFF] = widen4<T>(nm);
             if constexpr (WAVE) {
-                cp = np;
-                cb = nb;
+                cp = widen4<T>(np);
+                cb = widen4<T>(nb);
             }
         }
         s2 = s2 + 1 == NS2 ? 0 : s2 + 1;
