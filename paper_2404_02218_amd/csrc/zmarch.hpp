@@ -36,7 +36,7 @@ __device__ static inline int xcd_remap(int b, int nb) {
 }
 
 // -------------------------------------------------------------- k_zmarch
-// LDS holds a ring of R+2 plane slots of (TY+2R) x (TX+8) floats.  The halo
+// LDS holds a ring of R+2 plane slots of (TY+2R) x (TX+8) values.  The halo
 // part of a slot (the x and y margins of the tile) is written when its plane
 // is the leading plane z+R, i.e. when the neighbouring tiles load the same
 // rows as their own interior, so those rows are still in L2; the interior part
@@ -53,6 +53,36 @@ struct ZTile {
     static constexpr int NHX = 2 * TY, NHY = 2 * R * (TX / 4), NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
 };
 
+// LDS planes of BF16 fields hold the storage values as loaded (half the LDS
+// of FP32 planes, so more workgroups share a CU) and are widened per read,
+// which for BF16 is one shift or mask per value; FP32 and FP16 fields keep
+// FP32 planes (widening FP16 per read costs registers).  Values pass through
+// LDS unchanged either way.
+template <typename T>
+inline constexpr bool kLds16 = std::is_same<T, bf16>::value;
+template <typename T>
+using LdsT = typename std::conditional<kLds16<T>, T, float>::type;
+template <typename T>
+__device__ __forceinline__ float4 lds_get4(const LdsT<T>* p) {
+    if constexpr (kLds16<T>) return widen4<T>(*reinterpret_cast<const u2v*>(p));
+    else return *reinterpret_cast<const float4*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void lds_put4_raw(LdsT<T>* p, typename RawGroup<T>::type r) {
+    if constexpr (kLds16<T>) *reinterpret_cast<u2v*>(p) = r;
+    else *reinterpret_cast<float4*>(p) = widen4<T>(r);
+}
+// a group of 4 values that came from storage of type T (exact in T)
+template <typename T>
+__device__ __forceinline__ void lds_put4(LdsT<T>* p, float4 v) {
+    if constexpr (kLds16<T>) {
+        const u2v r = {Storage<T>::pack2(v.x, v.y), Storage<T>::pack2(v.z, v.w)};
+        *reinterpret_cast<u2v*>(p) = r;
+    } else {
+        *reinterpret_cast<float4*>(p) = v;
+    }
+}
+
 // Each thread owns VX consecutive x points (VX = 4 or 8) in VY rows strided
 // by BY; a row's VX values travel as VX/4 float4.
 template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
@@ -64,6 +94,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     constexpr int NV = VX / 4;
     constexpr bool WAVE = MODE != MODE_HEAT;
     using S = Storage<T>;
+    using LT = LdsT<T>;
+    LT* const ldsT = reinterpret_cast<LT*>(lds);
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = tid / BX;
@@ -136,10 +168,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
         for (int j = 0; j < VY; j++) load_vec<T, VX>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j], false);
     for (int p = zb; p < min(zb + R, ze); p++) {
-        float* L = lds + ((p - zb) % NSLOT) * PLANE;
+        LT* L = ldsT + ((p - zb) % NSLOT) * PLANE;
 #pragma unroll
         for (int m = 0; m < NH; m++)
-            if (hon[m]) *reinterpret_cast<float4*>(&L[hlds[m]]) = S::load4(U + (int64_t)p * sz + hoff[m]);
+            if (hon[m]) lds_put4_raw<T>(&L[hlds[m]], load4_raw<T, false>(U + (int64_t)p * sz + hoff[m]));
     }
     // loads in flight across a plane's compute stay in the storage type
     using Raw = typename RawGroup<T>::type;
@@ -187,17 +219,17 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     auto step = [&](auto off_c) {
         constexpr int OFF = decltype(off_c)::value;
         auto qi = [&](int k) -> float4(&)[VY][NV] { return q[(k + OFF) % Q]; };
-        float* L = lds + slot * PLANE;
+        LT* L = ldsT + slot * PLANE;
 #pragma unroll
         for (int j = 0; j < VY; j++)
 #pragma unroll
             for (int c = 0; c < NV; c++)
-                *reinterpret_cast<float4*>(&L[(R + ty + j * BY) * LDX + 4 + VX * tx + 4 * c]) = qi(R)[j][c];
+                lds_put4<T>(&L[(R + ty + j * BY) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
         if (z + R < ze) {
-            float* H = lds + hslot * PLANE;
+            LT* H = ldsT + hslot * PLANE;
 #pragma unroll
             for (int m = 0; m < NH; m++)
-                if (hon[m]) *reinterpret_cast<float4*>(&H[hlds[m]]) = widen4<T>(hal[m]);
+                if (hon[m]) lds_put4_raw<T>(&H[hlds[m]], hal[m]);
         }
 
         const bool more = z + 1 < ze;
@@ -228,12 +260,12 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
         for (int j = 0; j < VY; j++) {
             const int row = R + ty + j * BY;
-            const float* Lr = L + row * LDX + VX * tx;
+            const LT* Lr = L + row * LDX + VX * tx;
             // x taps: 4 left of the thread's points, its own VX, 4 right
             float xv[VX + 8];
             {
-                const float4 xl = *reinterpret_cast<const float4*>(Lr);
-                const float4 xr = *reinterpret_cast<const float4*>(Lr + 4 + VX);
+                const float4 xl = lds_get4<T>(Lr);
+                const float4 xr = lds_get4<T>(Lr + 4 + VX);
                 xv[0] = xl.x;
                 xv[1] = xl.y;
                 xv[2] = xl.z;
@@ -250,8 +282,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             for (int k = 1; k <= R; k++)
 #pragma unroll
                 for (int c = 0; c < NV; c++) {
-                    ym[k - 1][c] = *reinterpret_cast<const float4*>(L + (row - k) * LDX + 4 + VX * tx + 4 * c);
-                    yp[k - 1][c] = *reinterpret_cast<const float4*>(L + (row + k) * LDX + 4 + VX * tx + 4 * c);
+                    ym[k - 1][c] = lds_get4<T>(L + (row - k) * LDX + 4 + VX * tx + 4 * c);
+                    yp[k - 1][c] = lds_get4<T>(L + (row + k) * LDX + 4 + VX * tx + 4 * c);
                 }
 #pragma unroll
             for (int i = 0; i < VX; i++) {
@@ -419,7 +451,7 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 template <int MODE, int R, typename T, int C>
 static hipError_t zm_launch(const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(LdsT<T>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     const int64_t nb = zmarch_blocks(v);
     if (nb == 0) return hipSuccess;
     auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
@@ -456,7 +488,7 @@ template <int R, typename T, int C>
 static hipError_t zb_launch(const ZView* views, const int* bmap, int nblocks, const Coefs& w, int parity, int arow,
                             int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(float) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(LdsT<T>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     if (nblocks == 0) return hipSuccess;
     auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(k, lds);
