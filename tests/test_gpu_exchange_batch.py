@@ -97,18 +97,19 @@ def test_decomposed_equals_monolithic_on_gpu(device, parts, periodic):
     assert np.array_equal(out, ma)
 
 
-@pytest.mark.parametrize("steps", [17, 14])
-def test_batched_equals_sequential_bitwise(device, steps):
+@pytest.mark.parametrize("steps,dtype", [(17, S.F32), (14, S.F32), (17, S.BF16), (14, S.F16)])
+def test_batched_equals_sequential_bitwise(device, steps, dtype):
     # plain batched variants and the temporally blocked ones (tb2_*: two-step
-    # passes over all shots, plain batched sweeps for the remaining steps)
+    # passes over all shots, plain batched sweeps for the remaining steps),
+    # for FP32 and 16-bit storage
     import torch
     shapes = [(20, 33, 45), (37, 16, 70), (28, 28, 28), (9, 40, 12), (40, 70, 130)]
-    bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
+    bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8), dtype=dtype)
     tb = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("tb2_")]
     assert len(tb) == 3
     fields, srcs, amps, recs, trs, ins = [], [], [], [], [], []
     for i, sh in enumerate(shapes):
-        u0, um1, beta = wave_inputs(sh, seed=100 + i)
+        u0, um1, beta = wave_inputs(sh, seed=100 + i, dtype=dtype)
         ins.append((u0, um1, beta))
         f = [bp.field(i) for _ in range(3)]
         for fld, a in zip(f, (u0, um1, beta)):
@@ -126,7 +127,7 @@ def test_batched_equals_sequential_bitwise(device, steps):
         bp.run(fields, steps, srcs, amps, recs, trs)
         torch.cuda.synchronize()
         for i, sh in enumerate(shapes):
-            plan = S.Plan(S.WAVE2, sh, 4, S.second_derivative_weights(8), halo=4)
+            plan = S.Plan(S.WAVE2, sh, 4, S.second_derivative_weights(8), halo=4, dtype=dtype)
             a, b, tr = gpu_wave(plan, *ins[i], steps, src=srcs[i], amp=amps[i].cpu().numpy(),
                                 rec=recs[i])
             assert np.array_equal(fields[i][0].interior(4), a), (v, i)
