@@ -190,6 +190,29 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
     }
 
+    // adjoint: D and G of this thread's groups that lie wholly inside the
+    // interior, at the current plane; like u_prev and beta they are loaded a
+    // plane ahead, so their latency overlaps the compute (other groups read
+    // them at the store)
+    bool dg_ok[VY];
+    int64_t dg_off[VY];
+    float4 cd[VY][NV], cg[VY][NV];
+    if constexpr (MODE == MODE_WAVE_ADJ) {
+#pragma unroll
+        for (int j = 0; j < VY; j++) {
+            const int y = Y0 + ty + j * BY, x0 = X0 + VX * tx;
+            dg_ok[j] = y < ny && x0 + VX - 1 < nx;
+            dg_off[j] = v.g.origin + (int64_t)y * sy + x0;
+            if (dg_ok[j] && zb < ze) {
+#pragma unroll
+                for (int c = 0; c < NV; c++) {
+                    cd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
+                    cg[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
+                }
+            }
+        }
+    }
+
     // This tile's sources, sorted by z on the host: `snext` indexes the next
     // one at or after the chunk start and `szn` holds its z in a register, so
     // planes without a source cost one compare and no memory access (a load
@@ -234,6 +257,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 
         const bool more = z + 1 < ze;
         Raw np[VY][NV], nb[VY][NV];
+        float4 nd[VY][NV], ng[VY][NV];
         if (more) {
             const int64_t zn = (int64_t)(z + 1) * sz;
 #pragma unroll
@@ -249,6 +273,17 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     load_vec_raw<T, VX, NTH>(P + zn + own[j], np[j]);
                     load_vec_raw<T, VX, NTH>(B + zn + own[j], nb[j]);
                 }
+            }
+            if constexpr (MODE == MODE_WAVE_ADJ) {
+#pragma unroll
+                for (int j = 0; j < VY; j++)
+                    if (dg_ok[j]) {
+#pragma unroll
+                        for (int c = 0; c < NV; c++) {
+                            nd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + zn + 4 * c);
+                            ng[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + zn + 4 * c);
+                        }
+                    }
             }
         }
         __syncthreads();
@@ -379,8 +414,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     if (full) {
 #pragma unroll
                         for (int c = 0; c < NV; c++) {
-                            const float4 d = Storage<float>::load4_nt(D + 4 * c);
-                            float4 g = Storage<float>::load4_nt(G + 4 * c);
+                            const float4 d = cd[j][c];
+                            float4 g = cg[j][c];
                             g.x = fmaf(o[j][4 * c], d.x, g.x);
                             g.y = fmaf(o[j][4 * c + 1], d.y, g.y);
                             g.z = fmaf(o[j][4 * c + 2], d.z, g.z);
@@ -405,6 +440,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     if constexpr (WAVE) {
                         cp[j][c] = widen4<T>(np[j][c]);
                         cb[j][c] = widen4<T>(nb[j][c]);
+                    }
+                    if constexpr (MODE == MODE_WAVE_ADJ) {
+                        cd[j][c] = nd[j][c];
+                        cg[j][c] = ng[j][c];
                     }
                 }
         }
