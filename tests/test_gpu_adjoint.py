@@ -53,7 +53,7 @@ def _gpu(P, m, dobs, every, device, want_grad=True):
     scale = torch_f64(np.array([dt * dt / m[tuple(p)] for p in P["rec"]]), device)
     grad = torch.zeros(P["shape"], dtype=torch.float64, device=device)
     beta_f = plan.field().load(W.embed(beta, 4))
-    plan.adjoint(beta_f, steps, every, ws, resid, P["rec"], scale, -1.0 / (dt * dt), grad,
+    plan.adjoint(beta_f, steps, every, ws, resid, P["rec"], scale, dt, grad,
                  src=P["src"], src_amp=amp)
     torch.cuda.synchronize()
     return d, J, grad.cpu().numpy()
@@ -72,10 +72,11 @@ def test_gradient_matches_oracle(device, every):
     e_g = np.linalg.norm(g - rg) / np.linalg.norm(rg)
     print(f"checkpoint every {every}: traces {e_d:.2e}, misfit {e_J:.2e}, gradient rel L2 {e_g:.2e}")
     assert e_d <= 1e-5
-    # J and g are driven by residuals d - d_obs, much smaller than d itself, so
-    # the FP32 trace error (<= 1e-5 of max|d|) is amplified by max|d| / |d - d_obs|
-    assert e_J <= 5e-3
-    assert e_g <= 1e-3
+    # J and g are driven by residuals d - d_obs, smaller than d itself, so the
+    # FP32 trace error is amplified by max|d| / |d - d_obs|; measured about
+    # 1e-5 (misfit) and 5e-6 (gradient)
+    assert e_J <= 1e-4
+    assert e_g <= 1e-4
 
 
 def test_gradient_matches_gpu_central_differences(device):
@@ -90,8 +91,8 @@ def test_gradient_matches_gpu_central_differences(device):
     _, Jp, _ = _gpu(P, m0 + eps * dm, dobs, 25, device, want_grad=False)
     _, Jm, _ = _gpu(P, m0 - eps * dm, dobs, 25, device, want_grad=False)
     fd = (Jp - Jm) / (2 * eps)
-    print(f"J0 {J0:.6e}  FD {fd:.6e}  <g,dm> {gdm:.6e}")
-    assert abs(fd - gdm) <= 1e-2 * abs(gdm)
+    print(f"J0 {J0:.6e}  FD {fd:.6e}  <g,dm> {gdm:.6e}  rel {abs(fd - gdm) / abs(gdm):.2e}")
+    assert abs(fd - gdm) <= 1e-3 * abs(gdm)
 
 
 def test_recompute_equals_forward_bitwise(device):
@@ -134,7 +135,9 @@ def test_autograd_function_matches_direct_calls_and_fd(device):
         Jp = 0.5 * ((model(m0 + eps * dm) - d_obs) ** 2).sum().item()
         Jm = 0.5 * ((model(m0 - eps * dm) - d_obs) ** 2).sum().item()
     gdm = float((m0.grad * dm).sum())
-    assert abs((Jp - Jm) / (2 * eps) - gdm) <= 1e-2 * abs(gdm)
+    fd = (Jp - Jm) / (2 * eps)
+    print(f"autograd: FD {fd:.6e}  <g,dm> {gdm:.6e}  rel {abs(fd - gdm) / abs(gdm):.2e}")
+    assert abs(fd - gdm) <= 1e-3 * abs(gdm)
     # a backward after a newer forward is refused
     d3 = model(m0)
     model(m0.detach())

@@ -29,7 +29,14 @@ def _tuned_wave(P, dtype=S.F32, dn="f32"):
     return plan, f
 
 
-@pytest.mark.parametrize("dn", ["f32", "bf16"])
+# One sweep rounds the new level once to storage, and the source point once
+# more after the FP64 addition: each point is off by at most two unit
+# roundoffs of the largest level value (2^-8 BF16, 2^-11 FP16), plus FP32
+# arithmetic (well below 1e-5 of it).
+ONE_SWEEP_BOUND = {"f32": 1e-6, "bf16": 2 * 2.0 ** -8 + 1e-5, "f16": 2 * 2.0 ** -11 + 1e-5}
+
+
+@pytest.mark.parametrize("dn", ["f32", "bf16", "f16"])
 def test_c3_full_size_one_sweep_everywhere(device, dn):
     import torch
     dtype = S.DTYPES[dn]
@@ -51,7 +58,7 @@ def test_c3_full_size_one_sweep_everywhere(device, dn):
     ref[tuple(P.src[0])] += 3.5
     err = rel_err(got, ref)
     print(f"{dn}: one sweep at 512^3, variant {plan.variant_name(plan.variant)}: {err:.2e}")
-    assert err <= (1e-6 if dn == "f32" else 1e-2)
+    assert err <= ONE_SWEEP_BOUND[dn]
 
 
 def test_c3_full_size_light_cone_after_40_steps(device):
@@ -122,7 +129,7 @@ def test_c2_full_size_tuned_run_matches_oracle(device):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("dn", ["f32", "bf16"])
+@pytest.mark.parametrize("dn", ["f32", "bf16", "f16"])
 def test_c3_full_size_temporal_blocking_equals_plain_sweep(device, dn):
     """Six steps over the whole 512^3 field from random levels with the
     Ricker source: every temporally blocked variant (two-step passes, plus
@@ -214,7 +221,7 @@ def test_c5_full_size_gradient(device):
             return d, J, None
         g = torch.zeros(P.shape, dtype=torch.float64, device=device)
         scale = torch_f64(np.array([dt * dt / m[tuple(p)] for p in P.rec]), device)
-        plan.adjoint(f[2], N, k, ws, torch_f64(d - dobs, device), P.rec, scale, -1.0 / (dt * dt), g,
+        plan.adjoint(f[2], N, k, ws, torch_f64(d - dobs, device), P.rec, scale, dt, g,
                      src=P.src, src_amp=amp)
         torch.cuda.synchronize()
         return d, J, g.cpu().numpy()
@@ -229,9 +236,10 @@ def test_c5_full_size_gradient(device):
     _, Jp, _ = gpu(m0 + eps * dm, grad=False)
     _, Jm, _ = gpu(m0 - eps * dm, grad=False)
     fd = (Jp - Jm) / (2 * eps)
-    print(f"C5 256^3 x 500: traces vs oracle {e_tr:.2e}; J0 {J0:.6e}; FD {fd:.6e}; <g,dm> {gdm:.6e}")
+    print(f"C5 256^3 x 500: traces vs oracle {e_tr:.2e}; J0 {J0:.6e}; FD {fd:.6e}; <g,dm> {gdm:.6e}; "
+          f"rel {abs(fd - gdm) / abs(gdm):.2e}")
     assert e_tr <= 1e-5
     # the data must see the perturbation: a misfit far above FP32 noise
     assert J0 >= 1e-4 * 0.5 * float(np.sum(ref0 ** 2))
     assert abs(gdm) > 0 and abs(fd) > 0
-    assert abs(fd - gdm) <= 2e-2 * abs(gdm)
+    assert abs(fd - gdm) <= 1e-3 * abs(gdm)

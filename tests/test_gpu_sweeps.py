@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_2404_02218_amd as S
 import workloads as W
-from _helpers import gpu_heat, gpu_wave, oracle_wave, rel_err, wave_inputs
+from _helpers import gpu_heat, gpu_wave, oracle_wave, rel_err, torch_f64, wave_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +50,28 @@ def test_heat3d_so4_all_variants_bitwise_and_parity(device, shape):
     for v in range(1, plan.variant_count()):
         got = gpu_heat(plan, u0, 12, variant=v)
         assert np.array_equal(got, base), plan.variant_name(v)
+
+
+@pytest.mark.parametrize("radius", [1, 3, 4])
+def test_heat3d_other_radii_all_variants_bitwise_and_parity(device, radius):
+    """The z-marching and temporally blocked heat kernels are built for
+    radius 1..4 and the tuner may pick any of them: every variant gives
+    variant 0's bits on grids with ragged tiles, and variant 0 meets the
+    oracle."""
+    shape = (29, 37, 71)
+    rng = np.random.default_rng(22 + radius)
+    u0 = W.round_to_storage(rng.random(shape) + W.gaussian_bump(shape, 5.0), "f32")
+    alpha = 0.1 / radius
+    plan = S.Plan(S.HEAT, shape, radius, S.heat_weights(2 * radius, alpha), halo=radius)
+    base = gpu_heat(plan, u0, 10, variant=0)
+    c = [alpha * x for x in oracle.fd_weights_float(2 * radius)]
+    ref = W.interior_of(oracle.heat_run(W.embed(u0, radius), radius, radius, c, 10), radius)
+    assert rel_err(base, ref) <= TOL_F32
+    names = [plan.variant_name(v) for v in range(plan.variant_count())]
+    assert any(n.startswith("tb2_") for n in names)
+    for v in range(1, plan.variant_count()):
+        got = gpu_heat(plan, u0, 10, variant=v)
+        assert np.array_equal(got, base), names[v]
 
 
 def test_heat3d_periodic_fourier_mode(device):
@@ -207,3 +229,64 @@ def test_empty_interior_is_a_no_op(device):
     plan2 = S.Plan(S.HEAT, (0,), 1, S.heat_weights(2, 0.1))
     g = [plan2.field() for _ in range(2)]
     plan2.run(g, 3)
+
+
+def test_tune_cache_separates_boundary_conditions(device):
+    """A tuned Dirichlet plan's choice must not carry over to a periodic plan
+    of the same shape (the periodic halo refresh and the zero-halo kernels
+    differ): tune both, in that order, and check each run against the
+    oracle."""
+    shape3, alpha = (26, 34, 70), 0.05
+    rng = np.random.default_rng(91)
+    u3 = W.round_to_storage(rng.random(shape3), "f32")
+    c4 = [alpha * x for x in oracle.fd_weights_float(4)]
+    for bc, periodic in ((S.BC_DIRICHLET0, False), (S.BC_PERIODIC, True)):
+        plan = S.Plan(S.HEAT, shape3, 2, S.heat_weights(4, alpha), halo=2, bc=bc)
+        f = [plan.field() for _ in range(2)]
+        f[0].load(W.embed(u3, 2))
+        plan.tune(f, reps=1)
+        if periodic:
+            assert not plan.variant_name(plan.variant).startswith("tb2_")
+        got = gpu_heat(plan, u3, 8)
+        ref = W.interior_of(oracle.heat_run(W.embed(u3, 2), 2, 2, c4, 8, periodic=periodic), 2)
+        assert rel_err(got, ref) <= TOL_F32, (bc, plan.variant_name(plan.variant))
+    # 2D heat: the multi-step variants exist only with the zero halo
+    shape2 = (40, 56)
+    u2 = W.round_to_storage(rng.random(shape2), "f32")
+    c2 = [0.2 * x for x in oracle.fd_weights_float(2)]
+    for bc, periodic in ((S.BC_DIRICHLET0, False), (S.BC_PERIODIC, True)):
+        plan = S.Plan(S.HEAT, shape2, 1, S.heat_weights(2, 0.2), halo=1, bc=bc)
+        f = [plan.field() for _ in range(2)]
+        f[0].load(W.embed(u2, 1))
+        plan.tune(f, reps=1)
+        got = gpu_heat(plan, u2, 20)
+        ref = W.interior_of(oracle.heat_run(W.embed(u2, 1), 1, 1, c2, 20, periodic=periodic), 1)
+        assert rel_err(got, ref) <= TOL_F32, (bc, plan.variant_name(plan.variant))
+
+
+def test_rerun_with_coincident_sources_matches_oracle(device):
+    """A 2D wave run twice on the same fields, source table and amplitude
+    buffers, with the same number of sources: first at distinct positions,
+    then with several at one point (fewer position groups).  The second run
+    must not replay the first run's graph with the old group count."""
+    import torch
+    shape = (48, 70)
+    u0, um1, beta = wave_inputs(shape, seed=93, halo=4)
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    steps = 12
+    amp = torch_f64(np.random.default_rng(94).standard_normal((steps, 4)), device)
+    tr = torch.zeros((steps, 2), dtype=torch.float64, device=device)
+    rec = np.array([[24, 35], [10, 60]])
+    f = [plan.field() for _ in range(3)]
+    for src in (np.array([[10, 10], [20, 30], [30, 50], [40, 65]]),
+                np.array([[24, 35], [24, 35], [24, 35], [5, 5]]),
+                np.array([[10, 10], [20, 30], [30, 50], [40, 65]])):
+        f[0].load(W.embed(u0, 4))
+        f[1].load(W.embed(um1, 4))
+        f[2].load(W.embed(beta, 4))
+        tr.zero_()
+        plan.run(f, steps, src=src, src_amp=amp, rec=rec, rec_trace=tr)
+        torch.cuda.synchronize()
+        ra, rb, rtr = oracle_wave(u0, um1, beta, 4, 4, steps, src=src, amp=amp.cpu().numpy(), rec=rec)
+        assert rel_err(f[0].interior(4), ra) <= TOL_F32, src.tolist()
+        assert rel_err(tr.cpu().numpy(), rtr) <= TOL_F32, src.tolist()
