@@ -12,8 +12,12 @@ Also reported on the same GPU (`variants`):
     launch per step (one graph), against 32 sequential plain runs;
   * the checkpointed misfit gradient (256^3, 500 steps, 64 receivers,
     checkpoints every 25 steps) against the plain forward of the same model.
-`cpu_baseline` times the FP64 oracle on the host cores on a bounded sample of
-the headline workload (and, labelled as such, on one thread for two steps).
+`parity` compares the headline run with the FP64 oracle over all 400 steps,
+and `cpu_baseline` is that same oracle run's time on all host threads (the
+oracle compiled -O3 -march=native on the host; and, labelled as such, on one
+thread for two steps).  `roofline` prices each point update at the plain
+sweep's algorithmic bytes (u^n, u^{n-1}, beta read, u^{n+1} written: 16 B in
+FP32), times the updates of one launch of the dominant kernel.
 `runs` holds the median and minimum of the timed runs and the first run's
 time, which includes capturing the run's graph.
 
@@ -132,12 +136,15 @@ def stream_copy_gbs(nbytes=1 << 30, reps=10):
 
 
 def launch_model(vname, nsteps, es, storage):
-    """The dominant kernel of a wave run and its algorithmic bytes per launch
-    (per interior point).  Plain sweep: one launch per step reads u^n,
-    u^{n-1}, beta and writes u^{n+1} (4 fields).  Depth-2 temporal blocking:
-    one launch per two steps reads the same 3 fields and writes u^{n+1} and
-    u^{n+2} (5 fields); the runtime runs an even number of such passes and
-    plain sweeps for the remaining steps (none for 400 steps)."""
+    """The dominant kernel of a wave run: (temporally blocked?, launches per
+    run, the kernel's own bytes per launch per interior point, its name).
+    Plain sweep: one launch per step reads u^n, u^{n-1}, beta and writes
+    u^{n+1} (4 fields).  Depth-2 temporal blocking: one launch per two steps
+    reads the same 3 fields and writes u^{n+1} and u^{n+2} (5 fields); the
+    runtime runs an even number of such passes and plain sweeps for the
+    remaining steps (none for 400 steps).  The roofline itself prices every
+    point update at the plain sweep's 4 fields (the algorithmic bytes of one
+    update), so a launch of two steps counts 8 fields."""
     if vname.startswith("tb2_"):
         passes = nsteps // 2 - ((nsteps // 2) & 1)
         return True, passes + (nsteps - 2 * passes), 5 * es, f"k_tb2<{storage}>"
@@ -191,43 +198,85 @@ def time_wave(plan, f, amp, P, steps, warmup, per_run=None):
     return t.ms / steps
 
 
-def cpu_baseline(W, n, budget_s=20.0):
-    """FP64 oracle on the host cores: the headline recipe at its own n^3
-    interior, as many leapfrog steps as fit in about budget_s seconds."""
+def native_oracle():
+    """Build the FP64 oracle with -O3 -march=native for this host (the
+    in-tree build is for any x86-64 host) and load it; returns its path."""
+    import tempfile
+
+    import oracle
+    from oracle.build import build
+    path = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle_native.so")
+    build(native=True, out=path)
+    oracle.use_library(path)
+    return path
+
+
+def headline_oracle_run(S, W, plan, f, n, nsteps, final_timed, every=20):
+    """The headline run once more, on the GPU and in the FP64 oracle, in
+    segments of `every` steps (an even count, so the oracle's levels stay in
+    place): the error over the run (max over the levels at every segment end
+    of |gpu - oracle| over max |oracle|), the GPU's final levels against the
+    timed run's (bitwise), and the oracle's time on all host threads, which
+    is the CPU baseline of the full configuration."""
+    import torch
+
     import oracle
     threads = len(os.sched_getaffinity(0))
     os.environ["OMP_NUM_THREADS"] = str(threads)
-    P = W.wave3d_c3(n=n, nsteps=2)
-    beta = W.embed(W.round_to_storage(P.beta, "f32"), 4)
-    z = np.zeros_like(beta)
+    lib = native_oracle()
+    P = W.wave3d_c3(n=n, nsteps=nsteps)
+    bb = np.ascontiguousarray(W.embed(W.round_to_storage(P.beta, "f32"), 4))
+    a = np.zeros_like(bb)
+    b = np.zeros_like(bb)
     c = oracle.fd_weights_float(8)
-    t0 = time.perf_counter()
-    oracle.wave_run(z, z, beta, 4, 4, c, 2, src=P.src, src_amp=P.src_amp)
-    per = (time.perf_counter() - t0) / 2
-    k = max(2, min(400, int(budget_s / max(per, 1e-6))))
-    P = W.wave3d_c3(n=n, nsteps=k)
-    t0 = time.perf_counter()
-    oracle.wave_run(z, z, beta, 4, 4, c, k, src=P.src, src_amp=P.src_amp)
-    dt = time.perf_counter() - t0
-    out = {"value": round(float(n) ** 3 * k / dt / 1e9, 4), "unit": "GPts/s", "cores": threads,
+    f[0].zero()
+    f[1].zero()
+    num = den = 0.0
+    secs = 0.0
+    for t0 in range(0, nsteps, every):
+        k = min(every, nsteps - t0)
+        amp = np.ascontiguousarray(P.src_amp[t0:t0 + k])
+        plan.run(f, k, src=P.src, src_amp=torch.from_numpy(amp).cuda())
+        torch.cuda.synchronize()
+        got = f[0].interior(4)
+        t = time.perf_counter()
+        oracle.wave_run(a, b, bb, 4, 4, c, k, src=P.src, src_amp=amp, inplace=True)
+        secs += time.perf_counter() - t
+        ref = W.interior_of(a, 4)
+        num = max(num, float(np.max(np.abs(got - ref))))
+        den = max(den, float(np.max(np.abs(ref))))
+        del got
+    final = float(np.max(np.abs(f[0].interior(4) - W.interior_of(a, 4)))) / float(np.max(np.abs(W.interior_of(a, 4))))
+    same = bool(torch.equal(f[0].storage, final_timed[0]) and torch.equal(f[1].storage, final_timed[1]))
+    parity = {"error": num / den, "bound": 1e-5, "within_bound": bool(num / den <= 1e-5),
+              "final_level_error": final, "snapshot_every": every,
+              "metric": "max over the levels every 20 steps of |gpu - oracle| / max of |oracle|",
+              "segmented_run_bitwise_equal_to_timed_run": same,
+              "oracle": "FP64 C, OpenMP over z, -O3 -march=native on this host, fed the FP32-rounded beta"}
+    cpu = {"value": round(float(n) ** 3 * nsteps / secs / 1e9, 4), "unit": "GPts/s", "cores": threads,
            "kind": "oracle",
-           "sample": f"FP64 oracle (C, OpenMP over z), so-8 wave {n}^3 interior, first {k} of the "
-                     f"400 leapfrog steps, {dt:.1f} s"}
+           "sample": f"the full headline configuration: FP64 oracle (C, OpenMP over z, -O3 -march=native "
+                     f"on this host), so-8 wave {n}^3 interior, all {nsteps} leapfrog steps in segments of "
+                     f"{every}, {secs:.1f} s; the same run is the parity reference",
+           "library": os.path.basename(lib)}
     # one thread, two steps (labelled as such), and the host it ran on
     try:
         gomp = C.CDLL("libgomp.so.1")
         gomp.omp_set_num_threads(1)
         P1 = W.wave3d_c3(n=n, nsteps=2)
+        z = np.zeros_like(bb)
         t0 = time.perf_counter()
-        oracle.wave_run(z, z, beta, 4, 4, c, 2, src=P1.src, src_amp=P1.src_amp)
+        oracle.wave_run(z, z.copy(), bb, 4, 4, c, 2, src=P1.src, src_amp=P1.src_amp)
         d1 = time.perf_counter() - t0
         gomp.omp_set_num_threads(threads)
-        out["single_thread"] = {"value": round(float(n) ** 3 * 2 / d1 / 1e9, 4), "unit": "GPts/s",
+        cpu["single_thread"] = {"value": round(float(n) ** 3 * 2 / d1 / 1e9, 4), "unit": "GPts/s",
                                 "sample": f"the same oracle on one thread, first 2 steps, {d1:.1f} s"}
     except OSError:
         pass
-    out["host"] = host_cpu()
-    return out
+    cpu["host"] = host_cpu()
+    log(f"[bench] headline vs FP64 oracle over the run: {num / den:.3e} (final level {final:.3e}); "
+        f"oracle {secs:.1f} s on {threads} threads = {cpu['value']} GPts/s; bitwise == timed run: {same}")
+    return parity, cpu
 
 
 def host_cpu():
@@ -326,11 +375,13 @@ def bench_heat3d(S, W, steps, variant=-1, nsteps=50):
     # launches: a tb2 pass reads u^n and writes u^{n+2} (8 B per point for
     # two steps); a plain sweep moves 8 B per point for one step
     _, hl, _, _ = launch_model(hvn, H.nsteps, 4, "f32")
-    halg = 8.0 * npts * hl / (hms * 1e-3) / 1e9
-    log(f"[bench] heat {hvn}: {hms:.3f} ms per run, {hg:.1f} GPts/s, {halg:.0f} GB/s algorithmic")
+    hown = 8.0 * npts * hl / (hms * 1e-3) / 1e9
+    log(f"[bench] heat {hvn}: {hms:.3f} ms per run, {hg:.1f} GPts/s, {hg * 8:.0f} GB/s algorithmic "
+        f"(8 B per update), {hown:.0f} GB/s of the kernel's own bytes")
     return {"GPts_s": round(hg, 2), "ms_per_run": round(hms, 3), "steps": H.nsteps, "variant": hvn,
-            "launches_per_run": hl, "algorithmic_GBps": round(halg, 1), "frac_hbm": round(halg / HBM_PEAK_GBS, 4),
-            "effective_GBps_plain_sweep_bytes": round(hg * 8, 1)}
+            "launches_per_run": hl, "algorithmic_bytes_per_update": 8,
+            "algorithmic_GBps": round(hg * 8, 1), "frac_hbm": round(hg * 8 / HBM_PEAK_GBS, 4),
+            "kernel_own_GBps": round(hown, 1)}
 
 
 def bench_pw(S, W, steps, n=512, variant=-1):
@@ -704,7 +755,7 @@ def bench_adjoint(S, W, steps):
         f[0].storage.zero_()
         f[1].storage.zero_()
         plan.forward_ckpt(f, N, k, ws, src=P.src, src_amp=amp, rec=P.rec, rec_trace=tr)
-        plan.adjoint(f[2], N, k, ws, tr, P.rec, scale, -1.0 / P.dt ** 2, grad, src=P.src, src_amp=amp)
+        plan.adjoint(f[2], N, k, ws, tr, P.rec, scale, P.dt, grad, src=P.src, src_amp=amp)
 
     fwd()
     with Timer() as t:
@@ -770,12 +821,16 @@ def main():
     per_run = {}
     ms = time_wave(plan, f, amp, P, args.steps, args.warmup, per_run)
     gpts = pts / (ms * 1e-3) / 1e9
-    tb, launches, bpl, kname = launch_model(vname, nsteps, es, args.storage)
+    tb, launches, own_bpl, kname = launch_model(vname, nsteps, es, args.storage)
+    steps_per_launch = 2 if tb else 1
     kern_ms = ms / launches
+    # algorithmic bytes of one launch: the plain sweep's 4 fields per point
+    # update, times the updates one launch makes
+    bpl = 4 * es * steps_per_launch
     achieved = float(bpl) * n ** 3 / (kern_ms * 1e-3) / 1e9
-    effective = 4.0 * es * pts / (ms * 1e-3) / 1e9
+    own = float(own_bpl) * n ** 3 / (kern_ms * 1e-3) / 1e9
     log(f"[bench] {ms:.2f} ms per run, {kern_ms * 1e3:.1f} us per launch, {gpts:.1f} GPts/s, "
-        f"{achieved:.0f} GB/s algorithmic, {effective:.0f} GB/s in plain-sweep bytes")
+        f"{achieved:.0f} GB/s algorithmic ({4 * es} B per update), {own:.0f} GB/s of the kernel's own bytes")
     traffic = stored_traffic(vname) if (n == 512 and args.storage == "f32") else None
     out = {
         "metric": METRIC, "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
@@ -792,12 +847,19 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": kname, "algorithmic_bytes_per_launch": bpl * n ** 3,
-                     "points_per_launch": n ** 3, "steps_per_launch": 2 if tb else 1,
+                     "algorithmic_bytes_per_update": 4 * es,
+                     "points_per_launch": n ** 3, "steps_per_launch": steps_per_launch,
                      "launches_per_run": launches, "avg_launch_us": round(kern_ms * 1e3, 2),
-                     "effective_GBps_plain_sweep_bytes": round(effective, 1)},
+                     "kernel_own_bytes_per_launch": own_bpl * n ** 3,
+                     "kernel_own_GBps": round(own, 1), "kernel_own_frac": round(own / HBM_PEAK_GBS, 4)},
     }
     if traffic:
         out["roofline"]["traffic_GBps"] = round(traffic / (kern_ms * 1e-3) / 1e9, 1)
+    if not args.no_cpu and not args.only_main:
+        log("[bench] headline run against the FP64 oracle (also the CPU baseline)")
+        final_timed = [f[0].storage.clone(), f[1].storage.clone()]
+        out["parity"], cpu = headline_oracle_run(S, W, plan, f, n, nsteps, final_timed)
+        del final_timed
     del f
     torch.cuda.empty_cache()
 
@@ -813,12 +875,13 @@ def main():
             g2 = pts / (ms2 * 1e-3) / 1e9
             vn2 = plan2.variant_name(plan2.variant)
             _, l2, b2, k2 = launch_model(vn2, nsteps, 2, name)
-            a2 = float(b2) * n ** 3 / (ms2 / l2 * 1e-3) / 1e9
+            a2 = 8.0 * pts / (ms2 * 1e-3) / 1e9
+            o2 = float(b2) * n ** 3 / (ms2 / l2 * 1e-3) / 1e9
             extras[f"wave_{name}"] = {
                 "GPts_s": round(g2, 2), "ms_per_run": round(ms2, 2), "variant": vn2, "kernel": k2,
+                "algorithmic_bytes_per_update": 8,
                 "algorithmic_GBps": round(a2, 1), "frac_hbm": round(a2 / HBM_PEAK_GBS, 4),
-                "effective_GBps_plain_sweep_bytes": round(8.0 * pts / (ms2 * 1e-3) / 1e9, 1),
-                "vs_fp32": round(g2 / gpts, 3)}
+                "kernel_own_GBps": round(o2, 1), "vs_fp32": round(g2 / gpts, 3)}
             del f2
             torch.cuda.empty_cache()
         log("[bench] heat so-4 512^3 x 50")
@@ -852,8 +915,7 @@ def main():
         out["variants"] = extras
 
     if not args.no_cpu and not args.only_main:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(W, n)
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

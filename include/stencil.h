@@ -77,16 +77,23 @@ typedef struct {
     int32_t reserved;
 } stencil_exchange;
 
-/* Point sources: after the sweep of step t, u^{t+1} at pos[s] becomes
- * round_T(fl64(u^{t+1}) + amp[t*n + s]).  pos: host, [n][3] interior
- * coordinates.  amp: device FP64, [nsteps][n]. */
+/* Point sources (Devito's sparse source operation, Section 5.1): after the
+ * sweep of step t, u^{t+1} at pos[s] becomes round_T(fl64(u^{t+1}) + q) with
+ * q = amp[t*n + s], or q = fl64(amp[t*n + s] * scale[s]) when scale is not
+ * NULL.  For the acoustic wave in m-form the amount is dt^2 v_s^2 w(t): pass
+ * the wavelet samples w as amp and dt^2 v_s^2 as scale
+ * (stencil_wave_point_scale forms it from m).  pos: host, [n][3] interior
+ * coordinates.  amp: device FP64, [nsteps][n].  scale: device FP64 [n] or
+ * NULL. */
 typedef struct {
     int64_t n;
     const int64_t* pos;
     const double* amp;
+    const double* scale;
 } stencil_source;
 
-/* Receivers: trace[t*n + r] = fl64(u^{t+1} at pos[r]) for t = 0..nsteps-1.
+/* Receivers (Devito's sparse interpolation of the wavefield, Section 5.1):
+ * trace[t*n + r] = fl64(u^{t+1} at pos[r]) for t = 0..nsteps-1.
  * pos: host [n][3] interior coordinates.  trace: device FP64 [nsteps][n]. */
 typedef struct {
     int64_t n;
@@ -118,13 +125,18 @@ typedef struct {
  * `halo` >= `radius` cells on every side of every axis (Section 4.1: the halo
  * must cover the largest stencil.access offset).  radius 1..4; `coeffs` holds
  * radius+1 host doubles c_0..c_r (heat: already scaled by a dt/h^2).  The plan
- * owns small device constants only; it allocates no field memory.
+ * owns small device tables only (positions, coefficients, a captured graph);
+ * every field-sized buffer, including the temporally blocked variants'
+ * second level pair, is caller memory (stencil_set_workspace).
  * Errors: E_INVALID for ndim/radius/halo/shape out of range or NULL pointers;
  * E_NOMEM if a field would exceed 2^40 elements. */
 stencil_status stencil_create(stencil_plan* out, stencil_kind kind, int ndim, const int64_t* shape,
                               int radius, const double* coeffs, int halo, stencil_dtype dtype,
                               stencil_bc bc);
 
+/* Release a plan and the device tables it owns (no passage of the paper:
+ * plan lifetime).  Caller memory (fields, workspaces) is untouched; work
+ * enqueued with the plan must have finished. */
 stencil_status stencil_destroy(stencil_plan plan);
 
 /* Field layout (the stencil.field bounds, Section 4.1), identical for every
@@ -157,7 +169,11 @@ stencil_status stencil_apply(stencil_plan plan, void* out, const void* const* in
  * captured into one HIP graph per (pointers, nsteps, variant, tables) and
  * replayed; with the environment variable STENCIL_NO_GRAPH set to a value
  * other than 0 they are enqueued directly instead (the same kernels and
- * bits). */
+ * bits).  The temporally blocked wave variants need a caller workspace
+ * (stencil_run_workspace / stencil_set_workspace); without one the call
+ * fails with STENCIL_E_STATE.  The plan keeps small device tables of
+ * positions and, for sources with scales, their formed amounts; it never
+ * allocates field memory. */
 stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream);
 
@@ -178,8 +194,8 @@ stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, con
  * or non-finite entries. */
 stencil_status stencil_wave_damping(stencil_plan plan, const double* profile);
 
-/* Corners and weights of n interpolated positions (pos as in
- * stencil_source_interp): corners [n][2^ndim][3] (first ndim entries set)
+/* Corners and weights of n interpolated positions (Devito's sparse
+ * operations off the grid, Section 5.1; pos as in stencil_source_interp): corners [n][2^ndim][3] (first ndim entries set)
  * and weights [n][2^ndim], host arrays.  Per axis with extent e:
  * base = min(floor(x), e - 2) (0 when e < 2) and f = x - base (0 when
  * e < 2); corner bit 0 is (base, weight 1 - f), bit 1 is
@@ -190,7 +206,8 @@ stencil_status stencil_wave_damping(stencil_plan plan, const double* profile);
 stencil_status stencil_interp_weights(stencil_plan plan, int64_t n, const double* pos, int64_t* corners,
                                       double* weights);
 
-/* stencil_run with interpolated sources and receivers.  After the sweep of
+/* stencil_run with interpolated sources and receivers (Devito's sparse
+ * source and receiver operations at real positions, Section 5.1).  After the sweep of
  * step t, source s adds w_c * amp[t*n + s] at each corner c, as a point
  * source of that amount.  Entries at a shared grid point are applied in
  * (source, corner) order.  Receiver r records trace[t*n + r], the sum over
@@ -229,13 +246,17 @@ stencil_status stencil_exchanges_box(stencil_plan plan, const int32_t* grid, con
                                      int periodic, stencil_exchange* out, int* n);
 
 /* Pack the send boxes of n exchanges (host array) from `field` into `buf`
- * (device), each box in C order, concatenated in declaration order.  The
+ * (device): the send half of a dmp.swap as lowered to MPI (Section 4.3,
+ * the send buffer filled from the box [at + src_offset, + size) of
+ * Section 4.2), each box in C order, concatenated in declaration order.  The
  * number of elements is the sum of the box volumes; buf has the field's
  * storage dtype.  One launch for all boxes. */
 stencil_status stencil_halo_pack(stencil_plan plan, const void* field, const stencil_exchange* ex,
                                  int n, void* buf, void* stream);
 
-/* Unpack `buf` (as produced by a partner's pack) into the receive boxes. */
+/* Unpack `buf` (as produced by a partner's pack) into the receive boxes
+ * [at, at + size): the receive half of the lowered dmp.swap (Sections 4.2,
+ * 4.3).  Same layout and error behaviour as stencil_halo_pack. */
 stencil_status stencil_halo_unpack(stencil_plan plan, void* field, const stencil_exchange* ex, int n,
                                    const void* buf, void* stream);
 
@@ -243,56 +264,110 @@ stencil_status stencil_halo_unpack(stencil_plan plan, void* field, const stencil
 
 /* A batch of independent wave problems (3D only) of uneven interior shapes
  * shapes[nshots][3], sharing radius, weights, halo and dtype.  Each shot
- * has its own fields (layout from stencil_batch_layout). */
+ * has its own fields (layout from stencil_batch_layout).  The paper has no
+ * batched form: each shot is the Section 6.1 wave sweep (the operations of
+ * stencil_run), and the batch only changes how the shots' tiles are
+ * launched, to amortise the per-launch overhead the paper measured on its
+ * GPU (Section 6.1) over many small problems. */
 stencil_status stencil_batch_create(stencil_plan* out, int nshots, const int64_t* shapes, int radius,
                                     const double* coeffs, int halo, stencil_dtype dtype);
+/* Field layout of shot `shot` of a batch (the stencil.field bounds of
+ * Section 4.1, as stencil_layout). */
 stencil_status stencil_batch_layout(stencil_plan batch, int shot, int64_t* extents, int64_t* strides,
                                     int64_t* offset, int64_t* bytes);
 
-/* nsteps sweeps of every shot: one launch per step covers the tiles of all
- * shots, and the nsteps launches are captured into one HIP graph.
- * fields[3*s + {0,1,2}] = shot s's {u_n, u_prev, beta}, permuted per shot as
- * in stencil_run.  src / rec: arrays of nshots entries, or NULL. */
+/* nsteps sweeps of every shot (Section 6.1 wave sweep per shot, as in
+ * stencil_run): one launch per step (two steps for the temporally blocked
+ * variant) covers the tiles of all shots, and the launches are captured
+ * into one HIP graph.  fields[3*s + {0,1,2}] = shot s's {u_n, u_prev, beta},
+ * permuted per shot as in stencil_run.  src / rec: arrays of nshots entries,
+ * or NULL.  The temporally blocked variant needs a workspace as
+ * stencil_run does (one field pair per shot). */
 stencil_status stencil_batch_run(stencil_plan batch, void** fields, int64_t nsteps,
                                  const stencil_source* src, const stencil_receivers* rec, void* stream);
 
 /* ------------------------------------------------------------- adjoint */
 
-/* Workspace bytes for stencil_forward_ckpt / stencil_adjoint (3D wave plans,
- * FP32 storage): the checkpoints (u^c, u^{c-1}) every checkpoint_every steps,
- * one segment of second differences, two recompute levels, two adjoint
- * levels and an FP32 imaging partial. */
+/* The adjoint path (Section 5.1: Devito derives adjoint operators for
+ * seismic inversion; the paper gives no derivation, so the discrete adjoint
+ * of the wave recurrence is derived here).  Forward step n in m-form, with
+ * m = 1/v^2 and beta = dt^2/(h^2 m):
+ *   m (u^{n+1} - 2u^n + u^{n-1}) - (dt^2/h^2) L u^n - dt^2 q^n = 0,
+ * u^0 = u^{-1} = 0.  For J = 1/2 sum_n |P u^n - d^n_obs|^2 the adjoint state
+ * solves the same sweep backwards in time driven by the residuals,
+ *   lam^{k-1} = 2 lam^k - lam^{k+1} + beta .* L lam^k + dt^2/m_r (d^k - d^k_obs)_r,
+ * lam^N = lam^{N+1} = 0 (L is symmetric for the star with a zero halo), and
+ *   dJ/dm = -(1/dt^2) sum_{n=0..N-1} lam^n .* (u^{n+1} - 2u^n + u^{n-1}).
+ * Forward levels are recomputed segment by segment from checkpoints
+ * (u^c, u^{c-1}) stored every checkpoint_every steps.  3D wave plans with
+ * FP32 storage and the zero halo only. */
+
+/* Workspace bytes of the adjoint path (Section 5.1 adjoint operators; the
+ * checkpointing is this library's) for stencil_forward_ckpt /
+ * stencil_adjoint / stencil_gradient: the checkpoints (u^c, u^{c-1}) every checkpoint_every
+ * steps, one segment of second differences, two recompute levels, two
+ * adjoint levels and an FP32 imaging partial (caller memory). */
 stencil_status stencil_adjoint_workspace(stencil_plan plan, int64_t nsteps, int64_t checkpoint_every,
                                          size_t* bytes);
 
-/* Forward run as stencil_run (fields = {u_n, u_prev, beta}), also storing
- * (u^c, u^{c-1}) for c = 0, k, 2k, ... into the workspace. */
+/* Forward run of the adjoint path (the Section 6.1 wave sweep as
+ * stencil_run, fields = {u_n, u_prev, beta}), also storing (u^c, u^{c-1})
+ * for c = 0, k, 2k, ... into the workspace. */
 stencil_status stencil_forward_ckpt(stencil_plan plan, void** fields, int64_t nsteps,
                                     int64_t checkpoint_every, const stencil_source* src,
                                     const stencil_receivers* rec, void* workspace,
                                     size_t workspace_bytes, void* stream);
 
-/* Gradient of the data misfit with respect to the squared slowness m
- * (beta = dt^2 / (h^2 m)), by the exact discrete adjoint of the leapfrog
- * recurrence: for k = N..1, lam^{k-1} = 2 lam^k - lam^{k+1} + beta .* L lam^k
- * + rec_scale[r] * resid[(k-1)*nrec + r] at receiver r; and
- * grad += grad_scale * sum_n lam^n .* (u^{n+1} - 2u^n + u^{n-1}).
+/* Gradient of the data misfit with respect to m by the discrete adjoint
+ * above (Section 5.1, adjoint operators):
+ *   lam^{k-1} = 2 lam^k - lam^{k+1} + beta .* L lam^k
+ *               + rec_scale[r] * resid[(k-1)*nrec + r] at receiver r,
+ *   grad += -(1/dt^2) sum_n lam^n .* (u^{n+1} - 2u^n + u^{n-1}).
  * The forward levels are recomputed segment by segment from the checkpoints
  * left in `workspace` by stencil_forward_ckpt with the same nsteps,
  * checkpoint_every, beta and sources.  For J = 1/2 |d - d_obs|^2:
- * resid = d - d_obs, rec_scale = dt^2 v_r^2, grad_scale = -1/dt^2.
+ * resid = d - d_obs and rec_scale = dt^2 / m_r (stencil_wave_point_scale).
+ * The forward and this backward are separate calls so that a caller can
+ * drive the backward with any trace gradient (torch.autograd); see
+ * stencil_gradient for the misfit and its gradient in one call.
  * beta: field layout.  resid, rec_scale: device FP64.  grad: device FP64,
  * dense interior [nz][ny][nx], accumulated into (not cleared). */
 stencil_status stencil_adjoint(stencil_plan plan, const void* beta, int64_t nsteps,
                                int64_t checkpoint_every, const stencil_source* src,
                                const stencil_receivers* rec, const double* resid,
-                               const double* rec_scale, double grad_scale, double* grad,
+                               const double* rec_scale, double dt, double* grad,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* The misfit J = 1/2 sum |d - d_obs|^2 and its gradient dJ/dm in one call
+ * (Section 5.1, adjoint operators; the recurrences above): writes
+ * beta = dt^2/(h^2 m) into fields[2], zeroes fields[0] and fields[1]
+ * (u^0 = u^{-1} = 0), runs the checkpointed forward with source amounts
+ * dt^2/m_s * amp[t][s] (src->scale must be NULL: the scales come from m),
+ * records d into rec->trace, forms d - d_obs and J on the device, and runs
+ * the adjoint with receiver weights dt^2/m_r.  m: device FP64 dense interior.
+ * d_obs: device FP64 [nsteps][nrec].  misfit: device FP64, one value.  grad:
+ * device FP64 dense interior, overwritten.  fields is permuted as in
+ * stencil_run.  The workspace is that of stencil_adjoint_workspace; the plan
+ * keeps the point scales and the residual ((nsrc + nrec + nsteps * nrec)
+ * doubles).  Errors as stencil_forward_ckpt and stencil_adjoint, plus
+ * STENCIL_E_INVALID without receivers or with source scales. */
+stencil_status stencil_gradient(stencil_plan plan, void** fields, const double* m, double dt, double h,
+                                int64_t nsteps, int64_t checkpoint_every, const stencil_source* src,
+                                const stencil_receivers* rec, const double* d_obs, double* misfit,
+                                double* grad, void* workspace, size_t workspace_bytes, void* stream);
+
 /* beta = dt^2 / (h^2 m) on the interior of a field (halo untouched) from a
- * dense interior FP64 array m (device), rounded to the plan's dtype. */
+ * dense interior FP64 array m (device), rounded to the plan's dtype (the
+ * coefficient field of the Section 6.1 wave in terms of squared slowness). */
 stencil_status stencil_wave_beta(stencil_plan plan, const double* m, double dt, double h, void* beta,
                                  void* stream);
+
+/* out[i] = dt^2 / m(pos[i]) (FP64) for n interior positions (host [n][3]):
+ * the factor dt^2 v^2 of a source amount and of a receiver's residual
+ * weight in the m-form wave (Section 6.1 wave; Section 5.1 sparse sources).
+ * m: device FP64 dense interior.  out: device FP64 [n]. */
+stencil_status stencil_wave_point_scale(stencil_plan plan, const double* m, double dt, int64_t n,
+                                        const int64_t* pos, double* out, void* stream);
 
 /* ------------------------------------------------------- stencil programs */
 
@@ -312,7 +387,9 @@ typedef struct {
     double coeff;      /* rounded to FP32 for the device */
 } stencil_term;
 
-/* A program plan over interior `shape` (ndim 1..3) with halo `halo`: nin in
+/* A program plan (the several fused stencil.apply computations of Section
+ * 6.2, with stencil.access offsets of Section 4.1, as stencil_term
+ * describes) over interior `shape` (ndim 1..3) with halo `halo`: nin in
  * [1, 4] input and nout in [1, 4] output fields of FP32 storage sharing the
  * plan's layout (stencil_layout), nterms in [1, 64] terms (copied).  Every
  * offset must lie within min(halo, 2).  Errors: STENCIL_E_INVALID for bad
@@ -333,7 +410,8 @@ typedef struct {
 stencil_status stencil_program_create(stencil_plan* out, int ndim, const int64_t* shape, int halo, int nin,
                                       int nout, const stencil_term* terms, int nterms, stencil_dtype dtype);
 
-/* Evaluate the program once: outs[nout] and ins[nin] are device field
+/* Evaluate the program once (one fused stencil.apply region, Sections 4.1
+ * and 6.2): outs[nout] and ins[nin] are device field
  * pointers (256-byte aligned).  Interior points of every output are
  * written; halos are read from the inputs as they are (refresh them with an
  * exchange first where needed) and outputs' halos are untouched.  No output
@@ -400,9 +478,63 @@ typedef struct {
 stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfields, int loop,
                                 stencil_action* prologue, int* nprologue, stencil_action* body, int* nbody);
 
+/* ------------------------------------------- workspace and failure checks */
+
+/* Bytes of caller workspace the plan's current variant needs in stencil_run
+ * (stencil_batch_run for a batch): the second level pair of the temporally
+ * blocked wave sweep (two fields, one pair per shot for a batch; Section 7
+ * related work on overlapped temporal blocking), 0 for every other variant.
+ * Query again after stencil_tune or stencil_set_variant. */
+stencil_status stencil_run_workspace(stencil_plan plan, size_t* bytes);
+
+/* Attach caller device memory as the plan's run workspace (NULL detaches;
+ * no passage of the paper: memory ownership of the Section 7 temporal
+ * blocking's second level pair).
+ * The library enqueues a zero fill of all `bytes` on `stream` (the pair's
+ * halos must be zero) and then only writes interiors; the memory must stay
+ * valid while runs that use it may execute.  bytes: a multiple of 4. */
+stencil_status stencil_set_workspace(stencil_plan plan, void* workspace, size_t bytes, void* stream);
+
+/* Stability number of the plan's update (host only): D times the largest
+ * value over theta in [0, pi] of -(c_0 + 2 sum_k c_k cos k theta), the
+ * per-axis weights' symbol.  The explicit heat update is stable when it is
+ * <= 2; the leapfrog wave when beta_max times it is <= 4 (von Neumann
+ * analysis of the update of Section 5.1 / 6.1; the paper gives no bound). */
+stencil_status stencil_stability(stencil_plan plan, double* ds);
+
+typedef struct {
+    int64_t nan_count;  /* NaN values in the scanned levels' interiors */
+    int64_t inf_count;  /* infinite values there (storage overflow, e.g. past 65504 in FP16) */
+    double max_abs;     /* largest finite |value| there */
+    double beta_max;    /* wave: largest beta in the interior (0 for heat) */
+    double stability;   /* wave: beta_max * ds / 4; heat: ds / 2 (ds: stencil_stability); stable <= 1 */
+    double headroom;    /* largest finite value of the storage type / max_abs */
+    int32_t flags;      /* STENCIL_CHECK_* bits */
+    int32_t reserved;
+} stencil_check_report;
+
+enum {
+    STENCIL_CHECK_NONFINITE = 1, /* a level holds NaN or infinity */
+    STENCIL_CHECK_OVERFLOW = 2,  /* a level holds infinity: a value overflowed its storage type */
+    STENCIL_CHECK_UNSTABLE = 4,  /* stability > 1: the run grows without bound */
+    STENCIL_CHECK_BAD_BETA = 8   /* beta holds NaN or infinity */
+};
+
+/* On-demand scan of a sweep plan's fields (fields as in stencil_run; heat:
+ * fields[0]; wave: the levels fields[0], fields[1] and beta fields[2]) for
+ * non-finite values, their largest magnitude and the stability condition.
+ * A failure check (no passage of the paper: the method has no failure
+ * detection; the stability bound is the von Neumann one of
+ * stencil_stability).  Synchronises `stream`
+ * (the report is host data on return). */
+stencil_status stencil_check(stencil_plan plan, void* const* fields, stencil_check_report* out, void* stream);
+
 /* ------------------------------------------------------------ variants */
 
-/* Kernel variants of a plan.  Variant 0 is the one-thread-per-point kernel.
+/* Kernel variants of a plan (this library's kernel choices: no passage of
+ * the paper; the temporally blocked ones follow the overlapped temporal
+ * blocking of Section 7's related work).  Variant 0 is the
+ * one-thread-per-point kernel.
  * 3D plans add the z-marching sweep (tile shape and z-chunk), and for the
  * radius-4 wave and the FP32 heat with the zero halo the depth-2 temporally
  * blocked sweep (two steps per launch).  2D FP32 heat plans with the zero
@@ -413,18 +545,39 @@ stencil_status stencil_schedule(const stencil_step* steps, int nsteps, int nfiel
  * only; outputs go to a scratch field it allocates and frees) and keeps the
  * fastest per step of one launch (2D multi-step plans: per step of 96
  * steps captured in a graph, as runs execute them); the choice is cached per
- * (kind, ndim, radius, dtype, damping, shape).  For a program plan `fields`
+ * (device architecture, kind, ndim, radius, halo, boundary, dtype, damping,
+ * shapes, field bytes), as a variant name.  With STENCIL_TUNE_CACHE set to a
+ * file path the cache is read from that file on the first tuning of the
+ * process and every new choice is appended to it ("<arch> <key> <name>" per
+ * line); a cached name the plan does not offer is ignored and re-tuned.  With
+ * STENCIL_FORCE_VARIANT set to a variant name that the plan offers, tuning
+ * picks that variant without timing.  For a program plan `fields`
  * holds its nin input pointers, then its nout output pointers: the compiled
  * variants (0, 2 and 3 where it exists) are applied to them, the fastest
  * is kept, and the outputs hold the program's result (not cached; the
  * first apply of each variant compiles and loads it, outside capture). */
 stencil_status stencil_variant_count(stencil_plan plan, int* count);
+
+/* Name of variant `variant` (no passage of the paper: kernel choice), e.g.
+ * "tb2_64x32_t768_zc256", at most len - 1 characters. */
 stencil_status stencil_variant_name(stencil_plan plan, int variant, char* buf, size_t len);
+
+/* The plan's current variant (no passage of the paper: kernel choice). */
 stencil_status stencil_get_variant(stencil_plan plan, int* variant);
+
+/* Select a variant (no passage of the paper: kernel choice); every variant
+ * computes the same bits.  Batch plans take z-marching variants only. */
 stencil_status stencil_set_variant(stencil_plan plan, int variant);
+
+/* Time the candidates and keep the fastest, as described above (no passage
+ * of the paper: autotuning of the launch shape). */
 stencil_status stencil_tune(stencil_plan plan, void* const* fields, int reps, void* stream);
 
+/* Message of the last error on this thread (no passage of the paper: error
+ * reporting). */
 const char* stencil_last_error(void);
+
+/* Version of this ABI, 2 (no passage of the paper). */
 int stencil_abi_version(void);
 
 #ifdef __cplusplus

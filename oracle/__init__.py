@@ -39,6 +39,16 @@ class Exchange(C.Structure):
                 "src_offset": list(self.src_offset[:ndim]), "to": list(self.to[:ndim])}
 
 
+def use_library(path: str) -> None:
+    """Load the oracle from `path` (a build of the same source, e.g. one
+    compiled for the host's own instruction set) instead of the in-tree
+    library; must be called before the first oracle call."""
+    global _lib, _LIB_PATH
+    if _lib is not None:
+        raise OracleError("the oracle library is already loaded")
+    _LIB_PATH = path
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -124,11 +134,19 @@ def heat_run(u, halo, radius, c, nsteps, periodic=False):
 
 
 def wave_run(u_n, u_nm1, beta, halo, radius, c, nsteps, src=None, src_amp=None, rec=None,
-             periodic=False):
-    """nsteps leapfrog steps; returns (u^N, u^{N-1}, traces[N, nrec])."""
+             periodic=False, inplace=False):
+    """nsteps leapfrog steps; returns (u^N, u^{N-1}, traces[N, nrec]).  With
+    inplace=True the two levels must be C-contiguous FP64 arrays and are
+    advanced where they are (no copies)."""
     lib = _load()
-    a = _f64(u_n).copy()
-    b = _f64(u_nm1).copy()
+    if inplace:
+        for x in (u_n, u_nm1):
+            if x.dtype != np.float64 or not x.flags.c_contiguous:
+                raise OracleError("in-place levels must be C-contiguous FP64 arrays")
+        a, b = u_n, u_nm1
+    else:
+        a = _f64(u_n).copy()
+        b = _f64(u_nm1).copy()
     beta = _f64(beta)
     ndim = a.ndim
     shape = _shape_of(a, halo)

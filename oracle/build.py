@@ -14,15 +14,21 @@ SRC = os.path.join(HERE, "stencil_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
+    """Compile the oracle.  The in-tree library (the tests' reference) is
+    built for any x86-64 host; native=True builds -O3 -march=native for the
+    host that runs it (the CPU-baseline timing), into `out`.  ISO C mode
+    keeps floating-point contraction off, so both give the same FP64 bits."""
+    dest = out or LIB
+    tmp = dest + f".tmp{os.getpid()}"
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc", "-std=c11", *opt, "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, dest)
+    return dest
 
 
 if __name__ == "__main__":

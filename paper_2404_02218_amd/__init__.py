@@ -15,8 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (BC_DIRICHLET0, BC_PERIODIC, BF16, F16, F32, HEAT, WAVE2,  # noqa: F401
-                   Exchange, Receivers, ReceiversInterp, Source, SourceInterp, StencilError, call, lib)
+from ._abi import (BC_DIRICHLET0, BC_PERIODIC, BF16, CHECK_BAD_BETA, CHECK_NONFINITE,  # noqa: F401
+                   CHECK_OVERFLOW, CHECK_UNSTABLE, F16, F32, HEAT, WAVE2, CheckReport, Exchange, Receivers,
+                   ReceiversInterp, Source, SourceInterp, StencilError, call, lib)
 from .coeffs import damping_profile, heat_weights, second_derivative_weights  # noqa: F401
 
 DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
@@ -105,14 +106,16 @@ class Field:
 class _Points:
     """Keeps the ctypes structs and the host arrays they point to alive."""
 
-    def __init__(self, pos, dev):
+    def __init__(self, pos, dev, scale=None):
         self.pos, self.n = _positions(pos)
         self.dev = dev
+        self.scale = scale
 
     def source(self):
         if self.n == 0:
             return None
-        return Source(self.n, self.pos.ctypes.data_as(C.c_void_p), C.c_void_p(self.dev.data_ptr()))
+        sc = C.c_void_p(self.scale.data_ptr()) if self.scale is not None else None
+        return Source(self.n, self.pos.ctypes.data_as(C.c_void_p), C.c_void_p(self.dev.data_ptr()), sc)
 
     def receivers(self):
         if self.n == 0:
@@ -126,6 +129,24 @@ def _real_positions(pos, ndim):
     out = np.zeros((p.shape[0], 3), dtype=np.float64)
     out[:, :ndim] = p
     return np.ascontiguousarray(out)
+
+
+class _Workspace:
+    """Caller memory for a plan's run workspace (stencil_run_workspace /
+    stencil_set_workspace), grown when the plan's variant needs more."""
+
+    def __init__(self):
+        self.buf = None
+
+    def ensure(self, handle, stream=None):
+        b = C.c_size_t()
+        call("stencil_run_workspace", handle, C.byref(b))
+        need = b.value
+        if need == 0 or (self.buf is not None and self.buf.numel() >= need):
+            return
+        torch = _torch()
+        self.buf = torch.empty(need, dtype=torch.uint8, device=torch.cuda.current_device())
+        call("stencil_set_workspace", handle, C.c_void_p(self.buf.data_ptr()), need, _stream_ptr(stream))
 
 
 def _check_f64_device(t, shape, what):
@@ -152,6 +173,7 @@ class Plan:
              dtype, bc)
         self._h = h
         self.layout = self._layout()
+        self._ws = _Workspace()
 
     def _layout(self) -> Layout:
         e, s, o, b = (C.c_int64 * 3)(), (C.c_int64 * 3)(), C.c_int64(), C.c_int64()
@@ -181,16 +203,27 @@ class Plan:
         call("stencil_apply", self._h, C.c_void_p(out.ptr), ptrs, _i64(lo), _i64(hi),
              _stream_ptr(stream))
 
+    def run_workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        call("stencil_run_workspace", self._h, C.byref(b))
+        return b.value
+
     def run(self, fields: list, nsteps: int, src=None, src_amp=None, rec=None, rec_trace=None,
-            stream=None):
-        """nsteps sweeps; `fields` is permuted in place like the pointer array."""
+            stream=None, src_scale=None):
+        """nsteps sweeps; `fields` is permuted in place like the pointer array.
+        src_amp[t, s] is added at source s after step t, times src_scale[s]
+        when given (device FP64).  A variant that needs a run workspace gets
+        one allocated here (caller memory kept with the plan)."""
         ptrs = (C.c_void_p * 3)(*[f.ptr for f in fields] + [0] * (3 - len(fields)))
-        sp = _Points(src, src_amp)
+        sp = _Points(src, src_amp, src_scale)
         rp = _Points(rec, rec_trace)
         if sp.n:
             _check_f64_device(src_amp, (nsteps, sp.n), "src_amp")
+            if src_scale is not None:
+                _check_f64_device(src_scale, (sp.n,), "src_scale")
         if rp.n:
             _check_f64_device(rec_trace, (nsteps, rp.n), "rec_trace")
+        self._ws.ensure(self._h, stream)
         s, r = sp.source(), rp.receivers()
         call("stencil_run", self._h, ptrs, int(nsteps), C.byref(s) if s else None,
              C.byref(r) if r else None, _stream_ptr(stream))
@@ -306,11 +339,13 @@ class Plan:
         return b.value
 
     def forward_ckpt(self, fields, nsteps, every, workspace, src=None, src_amp=None, rec=None,
-                     rec_trace=None, stream=None):
+                     rec_trace=None, stream=None, src_scale=None):
         ptrs = (C.c_void_p * 3)(*[f.ptr for f in fields])
-        sp, rp = _Points(src, src_amp), _Points(rec, rec_trace)
+        sp, rp = _Points(src, src_amp, src_scale), _Points(rec, rec_trace)
         if sp.n:
             _check_f64_device(src_amp, (nsteps, sp.n), "src_amp")
+            if src_scale is not None:
+                _check_f64_device(src_scale, (sp.n,), "src_scale")
         if rp.n:
             _check_f64_device(rec_trace, (nsteps, rp.n), "rec_trace")
         s, r = sp.source(), rp.receivers()
@@ -322,11 +357,14 @@ class Plan:
             fields[0], fields[1] = fields[1], fields[0]
         return fields
 
-    def adjoint(self, beta: Field, nsteps, every, workspace, resid, rec, rec_scale, grad_scale,
-                grad, src=None, src_amp=None, stream=None):
-        sp, rp = _Points(src, src_amp), _Points(rec, None)
+    def adjoint(self, beta: Field, nsteps, every, workspace, resid, rec, rec_scale, dt,
+                grad, src=None, src_amp=None, stream=None, src_scale=None):
+        """grad += dJ/dm for the trace gradient `resid` (stencil_adjoint)."""
+        sp, rp = _Points(src, src_amp, src_scale), _Points(rec, None)
         if sp.n:
             _check_f64_device(src_amp, (nsteps, sp.n), "src_amp")
+            if src_scale is not None:
+                _check_f64_device(src_scale, (sp.n,), "src_scale")
         _check_f64_device(resid, (nsteps, rp.n), "resid")
         _check_f64_device(rec_scale, (rp.n,), "rec_scale")
         _check_f64_device(grad, self.shape, "grad")
@@ -334,9 +372,64 @@ class Plan:
         r = Receivers(rp.n, rp.pos.ctypes.data_as(C.c_void_p), None) if rp.n else None
         call("stencil_adjoint", self._h, C.c_void_p(beta.ptr), int(nsteps), int(every),
              C.byref(s) if s else None, C.byref(r) if r else None,
-             C.c_void_p(resid.data_ptr()), C.c_void_p(rec_scale.data_ptr()), float(grad_scale),
+             C.c_void_p(resid.data_ptr()), C.c_void_p(rec_scale.data_ptr()), float(dt),
              C.c_void_p(grad.data_ptr()), C.c_void_p(workspace.data_ptr()),
              workspace.numel() * workspace.element_size(), _stream_ptr(stream))
+
+    def gradient(self, fields, m, dt: float, h: float, nsteps: int, every: int, workspace, src, wavelet,
+                 rec, rec_trace, d_obs, misfit, grad, stream=None):
+        """Misfit and its gradient with respect to m in one call
+        (stencil_gradient): wavelet [nsteps, nsrc] FP64, d_obs and rec_trace
+        [nsteps, nrec], misfit a one-element FP64 tensor, grad the interior
+        shape; all device tensors.  `fields` is permuted like run()."""
+        ptrs = (C.c_void_p * 3)(*[f.ptr for f in fields])
+        sp, rp = _Points(src, wavelet), _Points(rec, rec_trace)
+        _check_f64_device(m, self.shape, "m")
+        if sp.n:
+            _check_f64_device(wavelet, (nsteps, sp.n), "wavelet")
+        _check_f64_device(rec_trace, (nsteps, rp.n), "rec_trace")
+        _check_f64_device(d_obs, (nsteps, rp.n), "d_obs")
+        _check_f64_device(misfit, (1,), "misfit")
+        _check_f64_device(grad, self.shape, "grad")
+        s, r = sp.source(), rp.receivers()
+        call("stencil_gradient", self._h, ptrs, C.c_void_p(m.data_ptr()), float(dt), float(h), int(nsteps),
+             int(every), C.byref(s) if s else None, C.byref(r) if r else None, C.c_void_p(d_obs.data_ptr()),
+             C.c_void_p(misfit.data_ptr()), C.c_void_p(grad.data_ptr()), C.c_void_p(workspace.data_ptr()),
+             workspace.numel() * workspace.element_size(), _stream_ptr(stream))
+        if ptrs[0] != fields[0].ptr:
+            fields[0], fields[1] = fields[1], fields[0]
+        return fields
+
+    def point_scale(self, m, dt: float, pos, stream=None):
+        """dt^2 / m at interior positions [n, ndim] (stencil_wave_point_scale):
+        a device FP64 tensor [n]."""
+        torch = _torch()
+        _check_f64_device(m, self.shape, "m")
+        p, n = _positions(pos)
+        out = torch.empty(max(n, 1), dtype=torch.float64, device=m.device)[:n]
+        call("stencil_wave_point_scale", self._h, C.c_void_p(m.data_ptr()), float(dt), n,
+             p.ctypes.data_as(C.c_void_p) if n else None, C.c_void_p(out.data_ptr()) if n else None,
+             _stream_ptr(stream))
+        return out
+
+    def stability(self) -> float:
+        """D times the largest symbol value of the weights (stencil_stability)."""
+        d = C.c_double()
+        call("stencil_stability", self._h, C.byref(d))
+        return d.value
+
+    def check(self, fields, stream=None) -> dict:
+        """Scan of the levels (and beta) for non-finite values, overflow and
+        the stability condition (stencil_check; synchronises the stream)."""
+        ptrs = (C.c_void_p * 3)(*[f.ptr for f in fields] + [0] * (3 - len(fields)))
+        rep = CheckReport()
+        call("stencil_check", self._h, ptrs, C.byref(rep), _stream_ptr(stream))
+        out = {k: getattr(rep, k) for k, _ in CheckReport._fields_ if k != "reserved"}
+        out["nonfinite"] = bool(rep.flags & CHECK_NONFINITE)
+        out["overflow"] = bool(rep.flags & CHECK_OVERFLOW)
+        out["unstable"] = bool(rep.flags & CHECK_UNSTABLE)
+        out["bad_beta"] = bool(rep.flags & CHECK_BAD_BETA)
+        return out
 
     def wave_beta(self, m, dt: float, h: float, beta: Field, stream=None):
         _check_f64_device(m, self.shape, "m")
@@ -357,6 +450,7 @@ class BatchPlan:
         call("stencil_batch_create", C.byref(h), len(self.shapes), sh.ctypes.data_as(C.c_void_p),
              radius, c, self.halo, dtype)
         self._h = h
+        self._ws = _Workspace()
         self.layouts = []
         for i in range(len(self.shapes)):
             e, s, o, b = (C.c_int64 * 3)(), (C.c_int64 * 3)(), C.c_int64(), C.c_int64()
@@ -424,6 +518,7 @@ class BatchPlan:
                 if p.n:
                     _check_f64_device(rec_traces[i], (nsteps, p.n), "rec_trace")
                     R[i] = p.receivers()
+        self._ws.ensure(self._h, stream)
         call("stencil_batch_run", self._h, ptrs, int(nsteps), S, R, _stream_ptr(stream))
         for i in range(ns):
             if ptrs[3 * i] != fields[i][0].ptr:

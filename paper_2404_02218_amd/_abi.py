@@ -63,11 +63,21 @@ class ReceiversInterp(C.Structure):
 
 
 class Source(C.Structure):
-    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p)]
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("amp", C.c_void_p), ("scale", C.c_void_p)]
 
 
 class Receivers(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("trace", C.c_void_p)]
+
+
+class CheckReport(C.Structure):
+    """stencil_check_report."""
+    _fields_ = [("nan_count", C.c_int64), ("inf_count", C.c_int64), ("max_abs", C.c_double),
+                ("beta_max", C.c_double), ("stability", C.c_double), ("headroom", C.c_double),
+                ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+CHECK_NONFINITE, CHECK_OVERFLOW, CHECK_UNSTABLE, CHECK_BAD_BETA = 1, 2, 4, 8
 
 
 EXPORTS = [
@@ -77,7 +87,9 @@ EXPORTS = [
     "stencil_program_create", "stencil_program_apply", "stencil_program_halo_dirs", "stencil_schedule",
     "stencil_batch_create",
     "stencil_batch_layout", "stencil_batch_run", "stencil_adjoint_workspace",
-    "stencil_forward_ckpt", "stencil_adjoint", "stencil_wave_beta", "stencil_variant_count",
+    "stencil_forward_ckpt", "stencil_adjoint", "stencil_gradient", "stencil_wave_beta",
+    "stencil_wave_point_scale", "stencil_run_workspace", "stencil_set_workspace", "stencil_stability",
+    "stencil_check", "stencil_variant_count",
     "stencil_variant_name", "stencil_get_variant", "stencil_set_variant", "stencil_tune",
     "stencil_last_error", "stencil_abi_version",
 ]
@@ -126,7 +138,13 @@ def lib():
         "stencil_adjoint_workspace": [P, I64, I64, P],
         "stencil_forward_ckpt": [P, P, I64, I64, P, P, P, C.c_size_t, P],
         "stencil_adjoint": [P, P, I64, I64, P, P, P, P, D, P, P, C.c_size_t, P],
+        "stencil_gradient": [P, P, P, D, D, I64, I64, P, P, P, P, P, P, C.c_size_t, P],
         "stencil_wave_beta": [P, P, D, D, P, P],
+        "stencil_wave_point_scale": [P, P, D, I64, P, P, P],
+        "stencil_run_workspace": [P, P],
+        "stencil_set_workspace": [P, P, C.c_size_t, P],
+        "stencil_stability": [P, P],
+        "stencil_check": [P, P, P, P],
         "stencil_variant_count": [P, P],
         "stencil_variant_name": [P, I, P, C.c_size_t],
         "stencil_get_variant": [P, P],

@@ -22,7 +22,7 @@ ARCH = os.environ.get("STENCIL_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 SOURCES = ["zmarch_tb.hip", "zmarch_tb_heat.hip", "zmarch_tb_damp.hip", "heat2d_tb.hip", "program.hip", "zmarch_f32.hip", "zmarch_adj.hip", "zmarch_bf16.hip", "zmarch_f16.hip",
-           "kernels.hip", "runtime.cpp", "program_rtc.cpp"]
+           "kernels.hip", "checks.hip", "runtime.cpp", "program_rtc.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -224,6 +224,15 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_beta(int dtype, const double* m, void* beta, const Grid3& g, double scale, hipStream_t s);
 hipError_t launch_flush(float* g32, double* grad, const Grid3& g, double scale, hipStream_t s);
 
+// checks.hip: out[i] = dt2 / m[off[i]]; the data residual and its misfit
+// 1/2 |trace - dobs|^2 (one workgroup, a fixed summation order); the scan of
+// a field's interior (out[0] += NaNs, out[1] += infinities, out[2] = max of
+// the largest finite |value| as the bits of a double)
+hipError_t launch_point_scale(const double* m, const int64_t* off, int64_t n, double dt2, double* out, hipStream_t s);
+hipError_t launch_misfit(const double* trace, const double* dobs, int64_t n, double* resid, double* misfit,
+                         hipStream_t s);
+hipError_t launch_scan(int dtype, const void* base, const Grid3& g, unsigned long long* out, hipStream_t s);
+
 // blocks of one z-marching launch over a field set
 inline int64_t zmarch_blocks(const ZView& v) { return (int64_t)v.ntx * v.nty * v.nzc; }
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -193,8 +194,36 @@ int default_variant(const Layout& L) {
     return 1;
 }
 
+// Tuning choices per (device architecture, plan key): the variant's name,
+// so that a cache file stays valid when variant numbers change.  Loaded once
+// from $STENCIL_TUNE_CACHE (if set) and appended to after each tuning.
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, std::string> g_tune_cache;
+bool g_tune_file_loaded = false;
+
+const char* tune_cache_path() {
+    const char* e = std::getenv("STENCIL_TUNE_CACHE");
+    return (e && e[0]) ? e : nullptr;
+}
+
+// caller holds g_tune_mu.  Lines: "<arch> <plan key> <variant name>".
+void load_tune_file() {
+    if (g_tune_file_loaded) return;
+    g_tune_file_loaded = true;
+    const char* path = tune_cache_path();
+    if (!path) return;
+    std::ifstream in(path);
+    std::string arch, key, name;
+    while (in >> arch >> key >> name) g_tune_cache[arch + " " + key] = name;
+}
+
+void store_tune_choice(const std::string& full_key, const std::string& name) {
+    g_tune_cache[full_key] = name;
+    const char* path = tune_cache_path();
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    if (out) out << full_key << " " << name << "\n";
+}
 
 }  // namespace
 
@@ -218,7 +247,20 @@ struct stencil_plan_s {
     bool variant_forced = false;
     PointTables src, rec, adjrec;
     PointTables src_ext;   // sources listed under every tile within R of them (temporal blocking)
-    DevBuf tb_pair[2];     // the second field pair of the temporally blocked sweep (zero halos)
+    // caller memory attached by stencil_set_workspace: the second field pair
+    // of the temporally blocked wave sweep (per shot for a batch), zero halos
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // source amounts scale[s] * amp[t][s] of a source with per-point scales
+    DevBuf amp_scaled;
+    std::vector<DevBuf> shot_amp_scaled;
+    // offsets of stencil_wave_point_scale (two tables, reused while their
+    // positions repeat) and of stencil_gradient's sources and receivers
+    DevTable ps_off[2], gsrc_off, grec_off;
+    int ps_next = 0;
+    // stencil_gradient: source and receiver scales, residual; stencil_check:
+    // NaN and infinity counts and the largest magnitude's bits
+    DevBuf gsrc_scale, grec_scale, gresid, scan;
     // interpolated sources and receivers (stencil_run_interp): corner
     // weights, the corners' amplitudes and the corner trace
     DevTable interp_sw, interp_rw;
@@ -240,7 +282,6 @@ struct stencil_plan_s {
     // batched temporal blocking: per-shot extended source lists, the second
     // field pair of every shot, and the view tables of even and odd passes
     std::vector<PointTables> shot_src_ext;
-    std::vector<DevBuf> shot_tb;   // 2 per shot
     DevTable tbviews[2];
     // stencil program
     int nin = 0, nout = 0, reach[3] = {0, 0, 0};
@@ -540,7 +581,7 @@ void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out) {
 }
 
 // Depth-2 temporally blocked run.  Each pass reads one field pair and
-// writes the other: the caller's (a, b) and the plan's tb_pair alternate, so
+// writes the other: the caller's (a, b) and the workspace pair alternate, so
 // an even number of passes leaves u^{2K} in a and u^{2K-1} in b, as 2K plain
 // in-place steps would.  Remaining steps (nsteps mod 4 of them when the pass
 // count would be odd, else nsteps mod 2) run as plain z-marching sweeps on
@@ -557,7 +598,7 @@ stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void*
     const float* damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
     int64_t passes = nsteps / 2;
     if (passes & 1) passes--;
-    void* pairs[2][2] = {{a, b}, {p->tb_pair[0].p, p->tb_pair[1].p}};
+    void* pairs[2][2] = {{a, b}, {p->ws, (char*)p->ws + round_up(L.bytes, 256)}};
     void* newest = a;
     void* prev = b;
     for (int64_t k = 0; k < passes; k++) {
@@ -727,7 +768,7 @@ bool graphs_enabled() {
 extern "C" {
 
 const char* stencil_last_error(void) { return g_err.c_str(); }
-int stencil_abi_version(void) { return 1; }
+int stencil_abi_version(void) { return 2; }
 
 stencil_status stencil_create(stencil_plan* out, stencil_kind kind, int ndim, const int64_t* shape, int radius,
                               const double* coeffs, int halo, stencil_dtype dtype, stencil_bc bc) {
@@ -861,28 +902,63 @@ static stencil_status prepare_points(stencil_plan p, const stencil_source* src, 
     return STENCIL_OK;
 }
 
-// the plan's second field pair, allocated with zero halos on first use
-// (before any capture: allocation and clearing synchronise the device)
-static stencil_status ensure_tb_pair(stencil_plan p) {
-    const size_t bytes = (size_t)p->L.bytes;
-    for (DevBuf& d : p->tb_pair) {
-        if (d.cap >= bytes && d.p) continue;
-        ST_TRY(d.ensure(bytes));
-        HIP_TRY(hipMemset(d.p, 0, d.cap));
-        HIP_TRY(hipDeviceSynchronize());
+// workspace bytes the plan's current variant needs: the second field pair
+// of the temporally blocked wave sweep (one pair per shot for a batch)
+static size_t run_workspace_bytes(const stencil_plan_s* p) {
+    const Variant var = variant_of(p->variant);
+    if (!var.tb) return 0;
+    if (p->batch) {
+        size_t b = 0;
+        for (const Layout& L : p->shots) b += 2 * (size_t)round_up(L.bytes, 256);
+        return b;
     }
+    if (p->kind != STENCIL_WAVE2 || p->ndim != 3) return 0;
+    return 2 * (size_t)round_up(p->L.bytes, 256);
+}
+
+static stencil_status check_workspace(const stencil_plan_s* p) {
+    const size_t need = run_workspace_bytes(p);
+    if (need > 0 && (!p->ws || p->ws_bytes < need))
+        return fail(STENCIL_E_STATE, "the temporally blocked variant needs a workspace of " + std::to_string(need) +
+                                         " bytes (stencil_run_workspace, stencil_set_workspace)");
     return STENCIL_OK;
 }
 
-static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+static stencil_status check_source_scale(const stencil_source* src) {
+    if (src && src->n > 0 && src->scale && ((uintptr_t)src->scale & 7))
+        return fail(STENCIL_E_INVALID, "source scales must be 8-byte aligned");
+    return STENCIL_OK;
+}
+
+// A source with per-point scales: its amounts scale[s] * amp[t][s] (FP64)
+// are formed once per call into `buf`, and `out` is the same source with
+// those amounts and no scales.  Sources without scales pass through.
+static stencil_status scaled_source(DevBuf& buf, const stencil_source* src, int64_t nsteps, stencil_source& out,
+                                    const stencil_source*& use, hipStream_t s) {
+    use = src;
+    if (!src || src->n == 0 || !src->scale) return STENCIL_OK;
+    ST_TRY(buf.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nsteps * src->n)));
+    HIP_TRY(launch_spread(src->amp, src->scale, 0, src->n, nsteps, (double*)buf.p, s));
+    out = *src;
+    out.amp = (const double*)buf.p;
+    out.scale = nullptr;
+    use = &out;
+    return STENCIL_OK;
+}
+
+static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src_in,
                                  const stencil_receivers* rec, void* stream) {
-    ST_TRY(run_args(p, fields, nsteps, src, rec));
-    ST_TRY(prepare_points(p, src, rec));
+    ST_TRY(run_args(p, fields, nsteps, src_in, rec));
+    ST_TRY(check_source_scale(src_in));
+    ST_TRY(check_workspace(p));
+    ST_TRY(prepare_points(p, src_in, rec));
     hipStream_t s = (hipStream_t)stream;
+    stencil_source scaled{};
+    const stencil_source* src = src_in;
+    ST_TRY(scaled_source(p->amp_scaled, src_in, nsteps, scaled, src, s));
     void* a = fields[0];
     void* b = fields[1];
     const void* beta = p->kind == STENCIL_WAVE2 ? fields[2] : nullptr;
-    if (variant_of(p->variant).tb && p->kind == STENCIL_WAVE2) ST_TRY(ensure_tb_pair(p));
     if (nsteps >= 2 && graphs_enabled()) {
         std::vector<int64_t> key = {(int64_t)(uintptr_t)a,
                                     (int64_t)(uintptr_t)b,
@@ -897,9 +973,10 @@ static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, 
                                     (int64_t)(uintptr_t)p->src.tiles.buf.p,
                                     (int64_t)(uintptr_t)p->src_ext.zyx4.buf.p,
                                     (int64_t)(uintptr_t)p->src_ext.tiles.buf.p,
-                                    (int64_t)(uintptr_t)p->tb_pair[0].p,
-                                    (int64_t)(uintptr_t)p->tb_pair[1].p,
+                                    (int64_t)(uintptr_t)p->ws,
                                     p->src.n,
+                                    p->src.ngrp,
+                                    p->src_ext.n,
                                     p->rec.n,
                                     (int64_t)(uintptr_t)p->src.grp.buf.p,
                                     (int64_t)(uintptr_t)p->src.gbeg.buf.p,
@@ -1394,7 +1471,7 @@ stencil_status stencil_batch_create(stencil_plan* out, int nshots, const int64_t
     p->shot_src.resize(nshots);
     p->shot_rec.resize(nshots);
     p->shot_src_ext.resize(nshots);
-    p->shot_tb.resize(2 * (size_t)nshots);
+    p->shot_amp_scaled.resize(nshots);
     // default: the 64x32 tile with 64-plane chunks
     p->variant = 1 + 2 * kNumTileCfgs + 0;
     *out = p;
@@ -1493,17 +1570,12 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
         // pass k reads pair k & 1 (newest, previous) and writes the other pair
         // (u^{n+2} into its first buffer, u^{n+1} into its second)
         std::vector<TBView> tv[2];
+        char* wsp = (char*)p->ws;
         for (int s = 0; s < ns; s++) {
             const Layout& L = p->shots[s];
-            const size_t bytes = (size_t)L.bytes;
-            for (int k = 0; k < 2; k++) {
-                DevBuf& d = p->shot_tb[2 * s + k];
-                if (d.p && d.cap >= bytes) continue;
-                ST_TRY(d.ensure(bytes));
-                HIP_TRY(hipMemset(d.p, 0, d.cap));
-                HIP_TRY(hipDeviceSynchronize());
-            }
-            void* pr[2][2] = {{fields[3 * s], fields[3 * s + 1]}, {p->shot_tb[2 * s].p, p->shot_tb[2 * s + 1].p}};
+            const int64_t fb = round_up(L.bytes, 256);
+            void* pr[2][2] = {{fields[3 * s], fields[3 * s + 1]}, {wsp, wsp + fb}};
+            wsp += 2 * fb;
             for (int par = 0; par < 2; par++) {
                 TBView t{};
                 t.u = pr[par][0];
@@ -1582,6 +1654,7 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
         if (src && src[s].n > 0) {
             ST_TRY(check_positions(p->shots[s], src[s].n, src[s].pos, "sources"));
             if (!src[s].amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+            ST_TRY(check_source_scale(&src[s]));
         }
         if (rec && rec[s].n > 0) {
             ST_TRY(check_positions(p->shots[s], rec[s].n, rec[s].pos, "receivers"));
@@ -1589,13 +1662,25 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
             any_rec = true;
         }
     }
+    ST_TRY(check_workspace(p));
     const Variant var = variant_of(p->variant);
-    std::vector<ZView> views;
-    ST_TRY(batch_prepare(p, fields, nsteps, src, rec, var, views));
     hipStream_t s = (hipStream_t)stream;
+    // shots whose sources carry per-point scales use their formed amounts
+    std::vector<stencil_source> srcs;
+    if (src) {
+        srcs.assign(src, src + ns);
+        for (int sh = 0; sh < ns; sh++) {
+            stencil_source tmp{};
+            const stencil_source* use = nullptr;
+            ST_TRY(scaled_source(p->shot_amp_scaled[sh], &src[sh], nsteps, tmp, use, s));
+            srcs[sh] = *use;
+        }
+    }
+    std::vector<ZView> views;
+    ST_TRY(batch_prepare(p, fields, nsteps, src ? srcs.data() : nullptr, rec, var, views));
     if (nsteps >= 2 && graphs_enabled()) {
         std::vector<int64_t> key = {nsteps, p->variant, (int64_t)(uintptr_t)p->views.buf.p, any_rec,
-                                    (int64_t)(uintptr_t)p->block_map.buf.p,
+                                    (int64_t)(uintptr_t)p->block_map.buf.p, (int64_t)(uintptr_t)p->ws,
                                     (int64_t)(uintptr_t)p->tbviews[0].buf.p, (int64_t)(uintptr_t)p->tbviews[1].buf.p};
         for (const ZView& v : views) {
             key.push_back((int64_t)(uintptr_t)v.u);
@@ -1692,19 +1777,13 @@ static Variant adjoint_variant(stencil_plan p) {
     return var;
 }
 
-stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nsteps, int64_t k, const stencil_source* src,
-                                    const stencil_receivers* rec, void* ws, size_t ws_bytes, void* stream) {
-    ST_TRY(check_sweep_plan(p));
-    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
-    AdjLayout A;
-    ST_TRY(adj_layout(p, nsteps, k, A));
-    ST_TRY(run_args(p, fields, nsteps, src, rec));
-    ST_TRY(check_ptr(ws, "workspace"));
-    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+// Forward run storing (u^c, u^{c-1}) every k steps (arguments validated)
+static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t nsteps, int64_t k,
+                                        const stencil_source* src, const stencil_receivers* rec, void* ws,
+                                        const AdjLayout& A, hipStream_t s) {
     const Variant var = adjoint_variant(p);
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src));
     ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
-    hipStream_t s = (hipStream_t)stream;
     const Layout& L = p->L;
     void* a = fields[0];
     void* b = fields[1];
@@ -1734,34 +1813,19 @@ stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nstep
     return STENCIL_OK;
 }
 
-stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps, int64_t k, const stencil_source* src,
-                               const stencil_receivers* rec, const double* resid, const double* rec_scale,
-                               double grad_scale, double* grad, void* ws, size_t ws_bytes, void* stream) {
-    ST_TRY(check_sweep_plan(p));
-    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
-    AdjLayout A;
-    ST_TRY(adj_layout(p, nsteps, k, A));
-    ST_TRY(check_ptr(beta, "beta"));
-    ST_TRY(check_ptr(ws, "workspace"));
-    if (!grad) return fail(STENCIL_E_INVALID, "grad is NULL");
-    if (!std::isfinite(grad_scale)) return fail(STENCIL_E_INVALID, "grad_scale must be finite");
-    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
-    if (src && src->n > 0) {
-        ST_TRY(check_positions(p->L, src->n, src->pos, "sources"));
-        if (!src->amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
-    }
-    const int64_t nrec = rec ? rec->n : 0;
-    if (nrec > 0) {
-        ST_TRY(check_positions(p->L, rec->n, rec->pos, "receivers"));
-        if (!resid || !rec_scale) return fail(STENCIL_E_INVALID, "resid and rec_scale are required with receivers");
-    }
+// Adjoint sweep with fused imaging over the checkpointed segments, last to
+// first (arguments validated); grad += -(1/dt^2) sum_n lam^n (u^{n+1} - 2u^n + u^{n-1})
+static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nsteps, int64_t k,
+                                   const stencil_source* src, int64_t nrec, const int64_t* rec_pos,
+                                   const double* resid, const double* rec_scale, double dt, double* grad, void* ws,
+                                   const AdjLayout& A, hipStream_t s) {
     const Variant var = adjoint_variant(p);
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src));
-    ST_TRY(build_points(p->L, nrec, nrec ? rec->pos : nullptr, var.cfg, p->adjrec));
-    hipStream_t s = (hipStream_t)stream;
+    ST_TRY(build_points(p->L, nrec, nrec ? rec_pos : nullptr, var.cfg, p->adjrec));
     const Layout& L = p->L;
     const SrcList fsrc = src_list(p->src, src ? src->amp : nullptr, nullptr);
     const SrcList asrc = src_list(p->adjrec, resid, rec_scale);
+    const double grad_scale = -1.0 / (dt * dt);
     void* F0 = slot(ws, A, A.f0);
     void* F1 = slot(ws, A, A.f1);
     void* L0 = slot(ws, A, A.l0);
@@ -1806,14 +1870,247 @@ stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps,
     return STENCIL_OK;
 }
 
+static stencil_status check_dt_h(double dt, double h) {
+    if (!(dt > 0) || !(h > 0) || !std::isfinite(dt) || !std::isfinite(h))
+        return fail(STENCIL_E_INVALID, "dt and h must be positive and finite");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_forward_ckpt(stencil_plan p, void** fields, int64_t nsteps, int64_t k, const stencil_source* src,
+                                    const stencil_receivers* rec, void* ws, size_t ws_bytes, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    ST_TRY(run_args(p, fields, nsteps, src, rec));
+    ST_TRY(check_source_scale(src));
+    ST_TRY(check_ptr(ws, "workspace"));
+    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    stencil_source scaled{};
+    const stencil_source* use = src;
+    ST_TRY(scaled_source(p->amp_scaled, src, nsteps, scaled, use, s));
+    return forward_ckpt_impl(p, fields, nsteps, k, use, rec, ws, A, s);
+}
+
+stencil_status stencil_adjoint(stencil_plan p, const void* beta, int64_t nsteps, int64_t k, const stencil_source* src,
+                               const stencil_receivers* rec, const double* resid, const double* rec_scale, double dt,
+                               double* grad, void* ws, size_t ws_bytes, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    ST_TRY(check_ptr(beta, "beta"));
+    ST_TRY(check_ptr(ws, "workspace"));
+    if (!grad) return fail(STENCIL_E_INVALID, "grad is NULL");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(STENCIL_E_INVALID, "dt must be positive and finite");
+    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+    if (src && src->n > 0) {
+        ST_TRY(check_positions(p->L, src->n, src->pos, "sources"));
+        if (!src->amp) return fail(STENCIL_E_INVALID, "source amplitudes are NULL");
+        ST_TRY(check_source_scale(src));
+    }
+    const int64_t nrec = rec ? rec->n : 0;
+    if (nrec > 0) {
+        ST_TRY(check_positions(p->L, rec->n, rec->pos, "receivers"));
+        if (!resid || !rec_scale) return fail(STENCIL_E_INVALID, "resid and rec_scale are required with receivers");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    stencil_source scaled{};
+    const stencil_source* use = src;
+    ST_TRY(scaled_source(p->amp_scaled, src, nsteps, scaled, use, s));
+    return adjoint_impl(p, beta, nsteps, k, use, nrec, nrec ? rec->pos : nullptr, resid, rec_scale, dt, grad, ws, A, s);
+}
+
 stencil_status stencil_wave_beta(stencil_plan p, const double* m, double dt, double h, void* beta, void* stream) {
     ST_TRY(check_sweep_plan(p));
     if (p->kind != STENCIL_WAVE2) return fail(STENCIL_E_STATE, "not a wave plan");
     if (!m) return fail(STENCIL_E_INVALID, "m is NULL");
     ST_TRY(check_ptr(beta, "beta"));
-    if (!(dt > 0) || !(h > 0) || !std::isfinite(dt) || !std::isfinite(h))
-        return fail(STENCIL_E_INVALID, "dt and h must be positive and finite");
+    ST_TRY(check_dt_h(dt, h));
     HIP_TRY(launch_beta(p->dtype, m, beta, p->L.g, dt * dt / (h * h), (hipStream_t)stream));
+    return STENCIL_OK;
+}
+
+// dense offsets of interior positions in an interior-shaped array
+static std::vector<int64_t> dense_offsets(const stencil_plan_s* p, int64_t n, const int64_t* pos) {
+    const Grid3& g = p->L.g;
+    std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1), 0);
+    for (int64_t i = 0; i < n; i++) {
+        int zyx[3];
+        zyx_of(p->L, pos + 3 * i, zyx);
+        off[(size_t)i] = ((int64_t)zyx[0] * g.n[1] + zyx[1]) * g.n[2] + zyx[2];
+    }
+    return off;
+}
+
+// the offsets in one of the plan's two point-scale tables: the one that
+// already holds them, else the one used less recently
+static stencil_status point_offsets(stencil_plan p, int64_t n, const int64_t* pos, const int64_t*& dev) {
+    const std::vector<int64_t> off = dense_offsets(p, n, pos);
+    const size_t bytes = sizeof(int64_t) * off.size();
+    for (int i = 0; i < 2; i++) {
+        DevTable& t = p->ps_off[i];
+        if (t.valid && t.host.size() == bytes && std::memcmp(t.host.data(), off.data(), bytes) == 0) {
+            dev = (const int64_t*)t.buf.p;
+            p->ps_next = 1 - i;
+            return STENCIL_OK;
+        }
+    }
+    DevTable& t = p->ps_off[p->ps_next];
+    p->ps_next ^= 1;
+    ST_TRY(t.upload(off.data(), bytes));
+    dev = (const int64_t*)t.buf.p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_wave_point_scale(stencil_plan p, const double* m, double dt, int64_t n, const int64_t* pos,
+                                        double* out, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    if (p->kind != STENCIL_WAVE2) return fail(STENCIL_E_STATE, "not a wave plan");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(STENCIL_E_INVALID, "dt must be positive and finite");
+    if (n < 0) return fail(STENCIL_E_INVALID, "n must be >= 0");
+    if (n == 0) return STENCIL_OK;
+    if (!m || !out) return fail(STENCIL_E_INVALID, "m and out are required");
+    ST_TRY(check_positions(p->L, n, pos, "positions"));
+    const int64_t* off = nullptr;
+    ST_TRY(point_offsets(p, n, pos, off));
+    HIP_TRY(launch_point_scale(m, off, n, dt * dt, out, (hipStream_t)stream));
+    return STENCIL_OK;
+}
+
+stencil_status stencil_gradient(stencil_plan p, void** fields, const double* m, double dt, double h, int64_t nsteps,
+                                int64_t k, const stencil_source* src, const stencil_receivers* rec, const double* d_obs,
+                                double* misfit, double* grad, void* ws, size_t ws_bytes, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    if (p->damped) return fail(STENCIL_E_UNSUPPORTED, "the adjoint path has no absorbing layer");
+    AdjLayout A;
+    ST_TRY(adj_layout(p, nsteps, k, A));
+    ST_TRY(run_args(p, fields, nsteps, src, rec));
+    ST_TRY(check_dt_h(dt, h));
+    if (!m) return fail(STENCIL_E_INVALID, "m is NULL");
+    if (src && src->n > 0 && src->scale)
+        return fail(STENCIL_E_INVALID, "source scales come from m here; pass the wavelet with scale NULL");
+    if (!rec || rec->n == 0) return fail(STENCIL_E_INVALID, "the misfit needs receivers");
+    if (!d_obs || !misfit || !grad) return fail(STENCIL_E_INVALID, "d_obs, misfit and grad are required");
+    ST_TRY(check_ptr(ws, "workspace"));
+    if (ws_bytes < (size_t)(A.slots * A.fbytes)) return fail(STENCIL_E_INVALID, "workspace too small");
+    const int64_t ns = src ? src->n : 0, nr = rec->n;
+    if (nsteps * nr > (int64_t(1) << 31)) return fail(STENCIL_E_NOMEM, "trace too large");
+    {
+        const std::vector<int64_t> so = dense_offsets(p, ns, ns ? src->pos : nullptr);
+        const std::vector<int64_t> ro = dense_offsets(p, nr, rec->pos);
+        ST_TRY(p->gsrc_off.upload(so.data(), sizeof(int64_t) * so.size()));
+        ST_TRY(p->grec_off.upload(ro.data(), sizeof(int64_t) * ro.size()));
+    }
+    const int64_t* soff = (const int64_t*)p->gsrc_off.buf.p;
+    const int64_t* roff = (const int64_t*)p->grec_off.buf.p;
+    ST_TRY(p->gsrc_scale.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, ns)));
+    ST_TRY(p->grec_scale.ensure(sizeof(double) * (size_t)nr));
+    ST_TRY(p->gresid.ensure(sizeof(double) * (size_t)(nsteps * nr)));
+    ST_TRY(p->amp_scaled.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nsteps * ns)));
+    hipStream_t s = (hipStream_t)stream;
+    const Layout& L = p->L;
+    // u^0 = u^{-1} = 0; beta = dt^2 / (h^2 m); the source amounts
+    // dt^2 / m_s * w(t) and receiver weights dt^2 / m_r
+    HIP_TRY(launch_zero(fields[0], L.bytes, s));
+    HIP_TRY(launch_zero(fields[1], L.bytes, s));
+    HIP_TRY(launch_beta(p->dtype, m, fields[2], L.g, dt * dt / (h * h), s));
+    HIP_TRY(launch_point_scale(m, roff, nr, dt * dt, (double*)p->grec_scale.p, s));
+    stencil_source scaled{};
+    const stencil_source* use = nullptr;
+    if (ns > 0) {
+        HIP_TRY(launch_point_scale(m, soff, ns, dt * dt, (double*)p->gsrc_scale.p, s));
+        HIP_TRY(launch_spread(src->amp, (const double*)p->gsrc_scale.p, 0, ns, nsteps, (double*)p->amp_scaled.p, s));
+        scaled = *src;
+        scaled.amp = (const double*)p->amp_scaled.p;
+        scaled.scale = nullptr;
+        use = &scaled;
+    }
+    ST_TRY(forward_ckpt_impl(p, fields, nsteps, k, use, rec, ws, A, s));
+    HIP_TRY(launch_misfit(rec->trace, d_obs, nsteps * nr, (double*)p->gresid.p, misfit, s));
+    HIP_TRY(launch_zero(grad, sizeof(double) * L.g.n[0] * L.g.n[1] * L.g.n[2], s));
+    return adjoint_impl(p, fields[2], nsteps, k, use, nr, rec->pos, (const double*)p->gresid.p,
+                        (const double*)p->grec_scale.p, dt, grad, ws, A, s);
+}
+
+// ------------------------------------------------ workspace, stability, checks
+stencil_status stencil_run_workspace(stencil_plan p, size_t* bytes) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (!bytes) return fail(STENCIL_E_INVALID, "bytes is NULL");
+    *bytes = p->program ? 0 : run_workspace_bytes(p);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_set_workspace(stencil_plan p, void* workspace, size_t bytes, void* stream) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (p->program) return fail(STENCIL_E_STATE, "program plans take no workspace");
+    if (!workspace) {
+        p->ws = nullptr;
+        p->ws_bytes = 0;
+        return STENCIL_OK;
+    }
+    ST_TRY(check_ptr(workspace, "workspace"));
+    if (bytes % 4) return fail(STENCIL_E_INVALID, "workspace bytes must be a multiple of 4");
+    HIP_TRY(launch_zero(workspace, (int64_t)bytes, (hipStream_t)stream));
+    p->ws = workspace;
+    p->ws_bytes = bytes;
+    return STENCIL_OK;
+}
+
+// Largest value over theta in [0, pi] of the symbol -(c0 + 2 sum_k c_k cos k theta)
+// of the per-axis weights (sampled finely, and exactly at 0 and pi), times D.
+static double stability_number(const stencil_plan_s* p) {
+    double best = 0.0;
+    const int ns = 4096;
+    for (int i = 0; i <= ns; i++) {
+        const double th = M_PI * i / ns;
+        double v = p->coeffs[0];
+        for (int k = 1; k <= p->radius; k++) v += 2.0 * p->coeffs[k] * std::cos(k * th);
+        best = std::max(best, -v);
+    }
+    return p->ndim * best;
+}
+
+stencil_status stencil_stability(stencil_plan p, double* ds) {
+    ST_TRY(check_sweep_plan(p));
+    if (!ds) return fail(STENCIL_E_INVALID, "ds is NULL");
+    *ds = stability_number(p);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_check(stencil_plan p, void* const* fields, stencil_check_report* out, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    if (!fields || !out) return fail(STENCIL_E_INVALID, "fields and out are required");
+    const bool wave = p->kind == STENCIL_WAVE2;
+    const int nlev = wave ? 2 : 1;
+    for (int f = 0; f < nlev + (wave ? 1 : 0); f++) ST_TRY(check_ptr(fields[f], "field"));
+    ST_TRY(p->scan.ensure(6 * sizeof(unsigned long long)));
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* d = (unsigned long long*)p->scan.p;
+    HIP_TRY(launch_zero(d, 6 * sizeof(unsigned long long), s));
+    for (int f = 0; f < nlev; f++) HIP_TRY(launch_scan(p->dtype, fields[f], p->L.g, d, s));
+    if (wave) HIP_TRY(launch_scan(p->dtype, fields[2], p->L.g, d + 3, s));
+    unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memset(out, 0, sizeof *out);
+    out->nan_count = (int64_t)h[0];
+    out->inf_count = (int64_t)h[1];
+    std::memcpy(&out->max_abs, &h[2], sizeof(double));
+    const double ds = stability_number(p);
+    if (wave) {
+        std::memcpy(&out->beta_max, &h[5], sizeof(double));
+        out->stability = out->beta_max * ds / 4.0;
+        if (h[3] || h[4]) out->flags |= STENCIL_CHECK_BAD_BETA;
+    } else {
+        out->stability = ds / 2.0;
+    }
+    const double fmax = p->dtype == STENCIL_F16 ? 65504.0 : 3.4028234663852886e38;
+    out->headroom = out->max_abs > 0 ? fmax / out->max_abs : HUGE_VAL;
+    if (out->nan_count || out->inf_count) out->flags |= STENCIL_CHECK_NONFINITE;
+    if (out->inf_count) out->flags |= STENCIL_CHECK_OVERFLOW;
+    if (out->stability > 1.0) out->flags |= STENCIL_CHECK_UNSTABLE;
     return STENCIL_OK;
 }
 
@@ -1873,16 +2170,40 @@ stencil_status stencil_set_variant(stencil_plan p, int variant) {
     return STENCIL_OK;
 }
 
+// Everything that decides which variants exist and how fast they run:
+// device architecture, plan kind, dimensions, radius, halo, boundary,
+// storage, damping and shapes (the field size also gates the temporally
+// blocked sweep).
 static std::string tune_key(stencil_plan p) {
-    std::string k = std::to_string(p->batch) + ":" + std::to_string(p->kind) + ":" + std::to_string(p->ndim) + ":" +
-                    std::to_string(p->radius) + ":" + std::to_string(p->dtype) + ":" + std::to_string(p->damped);
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        for (char& c : arch)
+            if (c == ' ') c = '_';
+    }
+    std::string k = arch + " b" + std::to_string(p->batch) + ":k" + std::to_string(p->kind) + ":d" +
+                    std::to_string(p->ndim) + ":r" + std::to_string(p->radius) + ":h" + std::to_string(p->halo) +
+                    ":bc" + std::to_string(p->bc) + ":t" + std::to_string(p->dtype) + ":damp" +
+                    std::to_string(p->damped);
     if (p->batch) {
         for (const Layout& L : p->shots)
             k += ":" + std::to_string(L.g.n[0]) + "x" + std::to_string(L.g.n[1]) + "x" + std::to_string(L.g.n[2]);
     } else {
         for (int a = 0; a < 3; a++) k += ":" + std::to_string(p->L.g.n[a]);
+        k += ":B" + std::to_string(p->L.bytes);
     }
     return k;
+}
+
+// the plan's variant called `name`, or -1
+static int variant_by_name(stencil_plan p, const std::string& name) {
+    const int n = variant_count_of(p);
+    char buf[96];
+    for (int v = p->batch ? 1 : 0; v < n; v++)
+        if (stencil_variant_name(p, v, buf, sizeof buf) == STENCIL_OK && name == buf) return v;
+    return -1;
 }
 
 // A 2D heat run is launch-bound: time 96 steps of variant `var` the way a run
@@ -1994,13 +2315,25 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     if (p->program) return tune_program(p, fields, reps, stream);
     int nvar = 0;
     ST_TRY(stencil_variant_count(p, &nvar));
+    if (const char* force = std::getenv("STENCIL_FORCE_VARIANT")) {
+        const int v = variant_by_name(p, force);
+        if (v >= 0) {
+            p->variant = v;
+            return STENCIL_OK;
+        }
+    }
     const std::string key = tune_key(p);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            p->variant = it->second;
-            return STENCIL_OK;
+            // a cached name this plan does not offer is ignored and re-tuned
+            const int v = variant_by_name(p, it->second);
+            if (v >= 0) {
+                p->variant = v;
+                return STENCIL_OK;
+            }
         }
     }
     if (nvar <= 1) return STENCIL_OK;
@@ -2155,8 +2488,11 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     (void)hipFree(scratch);
     if (st != STENCIL_OK) return st;
     p->variant = best;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best;
+    char name[96];
+    if (stencil_variant_name(p, best, name, sizeof name) == STENCIL_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        store_tune_choice(key, name);
+    }
     return STENCIL_OK;
 }
 

@@ -1,13 +1,14 @@
 """The so-8 acoustic wave forward model m -> receiver traces as a
 torch.autograd.Function.
 
-forward: beta = dt^2 / (h^2 m) is written by the library's kernel, the
-source amount dt^2 / m_s * w(t_n) is formed on the device, and the
-checkpointed forward run records the traces.  backward: the library's
-checkpointed adjoint sweep with fused imaging returns dJ/dm for the incoming
-trace gradient (for J = 1/2 |d - d_obs|^2 that gradient is d - d_obs).  The
-gradient is exact for the discrete recurrence in m-form, which already
-accounts for the source amount's dependence on m.
+forward: the library writes beta = dt^2 / (h^2 m) and the point scales
+dt^2 / m at the sources and receivers, injects the wavelet times the source
+scale, and records the traces in its checkpointed forward run.  backward: the
+library's checkpointed adjoint sweep with fused imaging returns dJ/dm for the
+incoming trace gradient (for J = 1/2 |d - d_obs|^2 that gradient is
+d - d_obs), with the receiver scales as residual weights.  The gradient is
+exact for the discrete recurrence in m-form, which already accounts for the
+source amount's dependence on m.  This module only marshals arguments.
 """
 from __future__ import annotations
 
@@ -35,22 +36,17 @@ class WaveModel:
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.wavelet = torch.as_tensor(np.asarray(wavelet, dtype=np.float64), device=self.device)
-        if self.wavelet.shape[0] != self.nsteps:
-            raise ValueError("wavelet must hold one sample per step")
+        w = np.asarray(wavelet, dtype=np.float64)
+        if w.ndim == 1:
+            w = np.repeat(w.reshape(-1, 1), len(self.src), axis=1)
+        if w.shape != (self.nsteps, len(self.src)):
+            raise ValueError("wavelet must hold one sample per step (per source, or shared)")
+        self.wavelet = torch.as_tensor(np.ascontiguousarray(w), device=self.device)
         self.plan = Plan(WAVE2, self.shape, 4, second_derivative_weights(8), halo=4)
         self.fields = [self.plan.field(self.device) for _ in range(3)]
         nbytes = self.plan.adjoint_workspace_bytes(self.nsteps, self.every)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.generation = 0
-        self._src_idx = self._flat(self.src)
-        self._rec_idx = self._flat(self.rec)
-
-    def _flat(self, pos):
-        import torch
-        nz, ny, nx = self.shape
-        idx = [(int(p[0]) * ny + int(p[1])) * nx + int(p[2]) for p in pos]
-        return torch.tensor(idx, dtype=torch.int64, device=self.device)
 
     def __call__(self, m):
         return WaveTraces.apply(m, self)
@@ -67,18 +63,16 @@ def _autograd_function():
             m = m.contiguous()
             plan, f, dt = model.plan, model.fields, model.dt
             plan.wave_beta(m, dt, model.h, f[2])
-            ms = m.reshape(-1).index_select(0, model._src_idx)
-            amp = ((dt * dt) / ms).reshape(1, -1) * model.wavelet.reshape(-1, 1)
-            amp = amp.contiguous()
+            src_scale = plan.point_scale(m, dt, model.src)
             tr = torch.zeros((model.nsteps, len(model.rec)), dtype=torch.float64, device=model.device)
             f[0].storage.zero_()
             f[1].storage.zero_()
             plan.forward_ckpt(f, model.nsteps, model.every, model.workspace, src=model.src,
-                              src_amp=amp, rec=model.rec, rec_trace=tr)
+                              src_amp=model.wavelet, rec=model.rec, rec_trace=tr, src_scale=src_scale)
             model.generation += 1
             ctx.model = model
             ctx.generation = model.generation
-            ctx.save_for_backward(m, amp)
+            ctx.save_for_backward(m, src_scale)
             return tr
 
         @staticmethod
@@ -87,14 +81,12 @@ def _autograd_function():
             if ctx.generation != model.generation:
                 raise RuntimeError("the model ran another forward since this one; its checkpoints "
                                    "are gone (one backward per forward)")
-            m, amp = ctx.saved_tensors
-            dt = model.dt
-            mr = m.reshape(-1).index_select(0, model._rec_idx)
-            scale = ((dt * dt) / mr).contiguous()
+            m, src_scale = ctx.saved_tensors
+            rec_scale = model.plan.point_scale(m, model.dt, model.rec)
             grad = torch.zeros_like(m)
             model.plan.adjoint(model.fields[2], model.nsteps, model.every, model.workspace,
-                               grad_traces.contiguous(), model.rec, scale, -1.0 / (dt * dt), grad,
-                               src=model.src, src_amp=amp)
+                               grad_traces.contiguous(), model.rec, rec_scale, model.dt, grad,
+                               src=model.src, src_amp=model.wavelet, src_scale=src_scale)
             return grad, None
 
     return _WaveTraces

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(_abi.EXPORTS) == names
-    assert lib.stencil_abi_version() == 1
+    assert lib.stencil_abi_version() == 2
 
 
 def _create(kind=S.WAVE2, shape=(8, 9, 10), radius=4, halo=4, dtype=S.F32, bc=S.BC_DIRICHLET0,
