@@ -214,8 +214,9 @@ stencil_status stencil_interp_weights(stencil_plan plan, int64_t n, const double
  * its corners c in order of w_c * fl64(u^{t+1} at c), as FP64 fused
  * multiply-adds.  The plan keeps the weights and a corner trace of
  * nsteps * n * 2^ndim doubles, allocated on first use and reused.  Sweep
- * plans only (not batched); errors as stencil_run, plus the position errors
- * of stencil_interp_weights. */
+ * plans only (not batched); the temporally blocked variants take the
+ * workspace as stencil_run does; errors as stencil_run, plus the position
+ * errors of stencil_interp_weights. */
 stencil_status stencil_run_interp(stencil_plan plan, void** fields, int64_t nsteps,
                                   const stencil_source_interp* src, const stencil_receivers_interp* rec,
                                   void* stream);

@@ -269,6 +269,7 @@ class Plan:
         if len(rp):
             _check_f64_device(rec_trace, (nsteps, len(rp)), "rec_trace")
             r = ReceiversInterp(len(rp), rp.ctypes.data_as(C.c_void_p), C.c_void_p(rec_trace.data_ptr()))
+        self._ws.ensure(self._h, stream)
         call("stencil_run_interp", self._h, ptrs, int(nsteps), C.byref(s) if s else None,
              C.byref(r) if r else None, _stream_ptr(stream))
         if ptrs[0] != fields[0].ptr:

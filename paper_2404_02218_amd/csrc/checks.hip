@@ -2,6 +2,7 @@
 // model's point scales dt^2 / m, the data residual and misfit, and the
 // on-demand scan of a field for non-finite values and its largest magnitude.
 #include <algorithm>
+#include <cstring>
 
 #include "kernels.hpp"
 
@@ -68,7 +69,35 @@ __global__ void k_scan(const T* base, Grid3 g, unsigned long long* out) {
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// A chunk of 32-bit words carried by value in the kernel's arguments, so
+// that host data reaches device memory without a host-to-device copy (and a
+// captured launch keeps its own copy of the data).
+constexpr int kFillWords = 512;
+struct FillChunk {
+    uint32_t n;
+    uint32_t w[kFillWords];
+};
+
+__global__ void k_fill_words(uint32_t* dst, FillChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
 }  // namespace
+
+hipError_t launch_fill_words(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    const uint32_t* from = (const uint32_t*)src;
+    uint32_t* to = (uint32_t*)dst;
+    for (size_t done = 0; done < bytes / 4; done += kFillWords) {
+        FillChunk c;
+        c.n = (uint32_t)std::min<size_t>(kFillWords, bytes / 4 - done);
+        std::memcpy(c.w, from + done, 4 * (size_t)c.n);
+        hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(256), 0, s, to + done, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_point_scale(const double* m, const int64_t* off, int64_t n, double dt2, double* out, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -232,6 +232,9 @@ hipError_t launch_point_scale(const double* m, const int64_t* off, int64_t n, do
 hipError_t launch_misfit(const double* trace, const double* dobs, int64_t n, double* resid, double* misfit,
                          hipStream_t s);
 hipError_t launch_scan(int dtype, const void* base, const Grid3& g, unsigned long long* out, hipStream_t s);
+// copy `bytes` (a multiple of 4) of host data to device memory through the
+// arguments of small kernels (512 words per launch)
+hipError_t launch_fill_words(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // blocks of one z-marching launch over a field set
 inline int64_t zmarch_blocks(const ZView& v) { return (int64_t)v.ntx * v.nty * v.nzc; }

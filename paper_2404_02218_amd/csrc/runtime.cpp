@@ -386,58 +386,77 @@ void zyx_of(const Layout& L, const int64_t* p3, int out[3]) {
     for (int d = 0; d < L.ndim; d++) out[3 - L.ndim + d] = (int)p3[d];
 }
 
-// Build the device tables of a point list for tile shape `cfg` (CSR over xy
-// tiles for the z-marching kernels; cfg < 0: offsets only).  ext > 0 lists a
-// point under every tile whose box widened by `ext` in x and y holds it.
-stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T, int ext = 0) {
-    T.n = (int)n;
-    std::vector<int64_t> off((size_t)std::max<int64_t>(n, 1));
-    for (int64_t i = 0; i < n; i++) off[i] = interior_offset(L, pos + 3 * i);
-    ST_TRY(T.off.upload(off.data(), sizeof(int64_t) * (size_t)n));
-    {
-        // entries by (position, index): coincident entries are applied in
-        // index order by one thread
-        std::vector<int> grp((size_t)std::max<int64_t>(n, 1)), gbeg(1, 0);
-        for (int64_t i = 0; i < n; i++) grp[i] = (int)i;
-        std::stable_sort(grp.begin(), grp.begin() + n, [&](int a, int b) { return off[a] < off[b]; });
-        for (int64_t k = 1; k <= n; k++)
-            if (k == n || off[grp[k]] != off[grp[k - 1]]) gbeg.push_back((int)k);
-        T.ngrp = (int)gbeg.size() - 1;
-        ST_TRY(T.grp.upload(grp.data(), sizeof(int) * (size_t)n));
-        ST_TRY(T.gbeg.upload(gbeg.data(), sizeof(int) * gbeg.size()));
+// Host tables of a point list for tile shape `cfg`: element offsets, the
+// entries grouped by position (coincident entries are applied in index order
+// by one thread), and for cfg >= 0 the CSR over xy tiles of the z-marching
+// kernels, entries sorted by (tile, z).  ext > 0 lists a point under every
+// tile whose box widened by `ext` in x and y holds it.
+struct HostPoints {
+    int n = 0, ngrp = 0;
+    bool tiled = false;
+    std::vector<int64_t> off;
+    std::vector<int> grp, gbeg, zyx4, tiles;
+};
+
+void host_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, HostPoints& H, int ext = 0) {
+    H = HostPoints{};
+    H.n = (int)n;
+    H.off.assign((size_t)std::max<int64_t>(n, 1), 0);
+    for (int64_t i = 0; i < n; i++) H.off[i] = interior_offset(L, pos + 3 * i);
+    H.grp.assign((size_t)std::max<int64_t>(n, 1), 0);
+    H.gbeg.assign(1, 0);
+    for (int64_t i = 0; i < n; i++) H.grp[i] = (int)i;
+    std::stable_sort(H.grp.begin(), H.grp.begin() + n, [&](int a, int b) { return H.off[a] < H.off[b]; });
+    for (int64_t k = 1; k <= n; k++)
+        if (k == n || H.off[H.grp[k]] != H.off[H.grp[k - 1]]) H.gbeg.push_back((int)k);
+    H.ngrp = (int)H.gbeg.size() - 1;
+    if (cfg < 0) return;
+    H.tiled = true;
+    const int TX = tile_tx(cfg), TY = tile_ty(cfg);
+    const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
+    const int nty = std::max(1, (L.g.n[1] + TY - 1) / TY);
+    // sort by (xy tile, z): the kernel walks a tile's sources in z order
+    std::vector<std::tuple<int, int, int>> order;
+    order.reserve((size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        int zyx[3];
+        zyx_of(L, pos + 3 * i, zyx);
+        const int ty0 = std::max(0, (zyx[1] - ext) / TY), ty1 = std::min(nty - 1, (zyx[1] + ext) / TY);
+        const int tx0 = std::max(0, (zyx[2] - ext) / TX), tx1 = std::min(ntx - 1, (zyx[2] + ext) / TX);
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++) order.emplace_back(ty * ntx + tx, zyx[0], (int)i);
     }
-    if (cfg >= 0) {
-        const int TX = tile_tx(cfg), TY = tile_ty(cfg);
-        const int ntx = std::max(1, (L.g.n[2] + TX - 1) / TX);
-        const int nty = std::max(1, (L.g.n[1] + TY - 1) / TY);
-        // sort by (xy tile, z): the kernel walks a tile's sources in z order
-        std::vector<std::tuple<int, int, int>> order;
-        order.reserve((size_t)n);
-        for (int64_t i = 0; i < n; i++) {
-            int zyx[3];
-            zyx_of(L, pos + 3 * i, zyx);
-            const int ty0 = std::max(0, (zyx[1] - ext) / TY), ty1 = std::min(nty - 1, (zyx[1] + ext) / TY);
-            const int tx0 = std::max(0, (zyx[2] - ext) / TX), tx1 = std::min(ntx - 1, (zyx[2] + ext) / TX);
-            for (int ty = ty0; ty <= ty1; ty++)
-                for (int tx = tx0; tx <= tx1; tx++) order.emplace_back(ty * ntx + tx, zyx[0], (int)i);
-        }
-        std::stable_sort(order.begin(), order.end());
-        const int64_t m = (int64_t)order.size();
-        std::vector<int> zyx4((size_t)std::max<int64_t>(4 * m, 4));
-        std::vector<int> tb((size_t)ntx * nty + 1, 0);
-        for (int64_t k = 0; k < m; k++) {
-            int zyx[3];
-            const int i = std::get<2>(order[k]);
-            zyx_of(L, pos + 3 * i, zyx);
-            zyx4[4 * k + 0] = zyx[0];
-            zyx4[4 * k + 1] = zyx[1];
-            zyx4[4 * k + 2] = zyx[2];
-            zyx4[4 * k + 3] = i;
-            tb[std::get<0>(order[k]) + 1]++;
-        }
-        for (size_t t = 1; t < tb.size(); t++) tb[t] += tb[t - 1];
-        ST_TRY(T.zyx4.upload(zyx4.data(), sizeof(int) * (size_t)(4 * m)));
-        ST_TRY(T.tiles.upload(tb.data(), sizeof(int) * tb.size()));
+    std::stable_sort(order.begin(), order.end());
+    const int64_t m = (int64_t)order.size();
+    H.zyx4.assign((size_t)std::max<int64_t>(4 * m, 4), 0);
+    H.tiles.assign((size_t)ntx * nty + 1, 0);
+    for (int64_t k = 0; k < m; k++) {
+        int zyx[3];
+        const int i = std::get<2>(order[k]);
+        zyx_of(L, pos + 3 * i, zyx);
+        H.zyx4[4 * k + 0] = zyx[0];
+        H.zyx4[4 * k + 1] = zyx[1];
+        H.zyx4[4 * k + 2] = zyx[2];
+        H.zyx4[4 * k + 3] = i;
+        H.tiles[std::get<0>(order[k]) + 1]++;
+    }
+    for (size_t t = 1; t < H.tiles.size(); t++) H.tiles[t] += H.tiles[t - 1];
+}
+
+// Build the device tables of a point list (host_points, uploaded to the
+// plan's tables).
+stencil_status build_points(const Layout& L, int64_t n, const int64_t* pos, int cfg, PointTables& T, int ext = 0) {
+    HostPoints H;
+    host_points(L, n, pos, cfg, H, ext);
+    T.n = H.n;
+    T.ngrp = H.ngrp;
+    ST_TRY(T.off.upload(H.off.data(), sizeof(int64_t) * (size_t)n));
+    ST_TRY(T.grp.upload(H.grp.data(), sizeof(int) * (size_t)n));
+    ST_TRY(T.gbeg.upload(H.gbeg.data(), sizeof(int) * H.gbeg.size()));
+    if (H.tiled) {
+        const int64_t m = H.tiles.back();
+        ST_TRY(T.zyx4.upload(H.zyx4.data(), sizeof(int) * (size_t)(4 * m)));
+        ST_TRY(T.tiles.upload(H.tiles.data(), sizeof(int) * H.tiles.size()));
     }
     T.cfg = cfg;
     return STENCIL_OK;
@@ -580,6 +599,22 @@ void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out) {
     out.push_back(cl);
 }
 
+// The point lists of one run: sources under their own tile (offsets and
+// position groups for the point kernel), sources under every tile within R
+// of them (temporal blocking) and receivers.
+struct RunLists {
+    SrcList st, se;
+    RecList rl;
+};
+
+RunLists plan_lists(stencil_plan p, const stencil_source* src, const stencil_receivers* rec) {
+    RunLists r;
+    r.st = src_list(p->src, src ? src->amp : nullptr, nullptr);
+    r.se = src_list(p->src_ext, src ? src->amp : nullptr, nullptr);
+    r.rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    return r;
+}
+
 // Depth-2 temporally blocked run.  Each pass reads one field pair and
 // writes the other: the caller's (a, b) and the workspace pair alternate, so
 // an even number of passes leaves u^{2K} in a and u^{2K-1} in b, as 2K plain
@@ -588,12 +623,11 @@ void periodic_copies(const Layout& L, int radius, std::vector<CopyList>& out) {
 // the same 64 x 32 tiles.  Receivers: pass k records its two input levels
 // (rows 2k-1 and 2k-2); the level u^{2K-1} is recorded after the last pass.
 stencil_status enqueue_run_tb(stencil_plan p, const Variant& var, void* a, void* b, const void* beta,
-                              int64_t nsteps, const stencil_source* src, const stencil_receivers* rec,
-                              hipStream_t s) {
+                              int64_t nsteps, const RunLists& RL, hipStream_t s) {
     const Layout& L = p->L;
-    const SrcList st = src_list(p->src, src ? src->amp : nullptr, nullptr);
-    const SrcList se = src_list(p->src_ext, src ? src->amp : nullptr, nullptr);
-    const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    const SrcList& st = RL.st;
+    const SrcList& se = RL.se;
+    const RecList& rl = RL.rl;
     const int mode = p->damped ? MODE_WAVE_DAMP : MODE_WAVE;
     const float* damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
     int64_t passes = nsteps / 2;
@@ -681,12 +715,12 @@ static stencil_status enqueue_run_heat2d(stencil_plan p, void* a, void* b, int64
 
 // Enqueue nsteps sweeps of a single plan (no capture logic here).
 stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, int64_t nsteps,
-                           const stencil_source* src, const stencil_receivers* rec, hipStream_t s) {
+                           const RunLists& RL, hipStream_t s) {
     const Layout& L = p->L;
     if (p->ndim == 2 && p->variant > 0 && heat2d_supported(p)) return enqueue_run_heat2d(p, a, b, nsteps, s);
     Variant var = variant_of(p->variant);
     const bool wave = p->kind == STENCIL_WAVE2;
-    if (var.tb && wave) return enqueue_run_tb(p, var, a, b, beta, nsteps, src, rec, s);
+    if (var.tb && wave) return enqueue_run_tb(p, var, a, b, beta, nsteps, RL, s);
     int64_t t0 = 0;
     if (var.tb) {
         // heat: an even number of two-step passes from one buffer into the
@@ -710,8 +744,8 @@ stencil_status enqueue_run(stencil_plan p, void* a, void* b, const void* beta, i
     }
     const int mode = wave ? (p->damped ? MODE_WAVE_DAMP : MODE_WAVE) : MODE_HEAT;
     const float* damp = p->damped ? (const float*)p->damp.buf.p : nullptr;
-    const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
-    const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
+    const SrcList& sl = RL.st;
+    const RecList& rl = RL.rl;
     std::vector<CopyList> per;
     if (p->bc == STENCIL_BC_PERIODIC) periodic_copies(L, p->radius, per);
     for (int64_t t = t0; t < nsteps; t++) {
@@ -990,7 +1024,7 @@ static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, 
                 p->gexec = nullptr;
             }
             HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-            stencil_status st = enqueue_run(p, a, b, beta, nsteps, src, rec, p->cap);
+            stencil_status st = enqueue_run(p, a, b, beta, nsteps, plan_lists(p, src, rec), p->cap);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(p->cap, &graph);
             if (st != STENCIL_OK) {
@@ -1008,7 +1042,7 @@ static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, 
         }
         HIP_TRY(hipGraphLaunch(p->gexec, s));
     } else {
-        ST_TRY(enqueue_run(p, a, b, beta, nsteps, src, rec, s));
+        ST_TRY(enqueue_run(p, a, b, beta, nsteps, plan_lists(p, src, rec), s));
     }
     if (nsteps & 1) std::swap(fields[0], fields[1]);
     return STENCIL_OK;
@@ -1097,6 +1131,7 @@ stencil_status stencil_interp_weights(stencil_plan p, int64_t n, const double* p
 stencil_status stencil_run_interp(stencil_plan p, void** fields, int64_t nsteps, const stencil_source_interp* src,
                                   const stencil_receivers_interp* rec, void* stream) {
     ST_TRY(check_sweep_plan(p));
+    ST_TRY(check_workspace(p));
     const int nd = p->ndim, nc = 1 << nd;
     const int64_t ns = src ? src->n : 0, nr = rec ? rec->n : 0;
     std::vector<int64_t> sp, rp;
