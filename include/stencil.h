@@ -177,6 +177,26 @@ stencil_status stencil_apply(stencil_plan plan, void* out, const void* const* in
 stencil_status stencil_run(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
                            const stencil_receivers* rec, void* stream);
 
+/* stencil_run for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results (bit for bit) and kernels as stencil_run, but it
+ * calls no hipMalloc, hipFree or other allocating routine and captures no
+ * graph of its own (it enqueues the sweeps directly).  The position tables
+ * of the sources and receivers, and the formed amounts of sources with
+ * scales, go into a static device array of 8 MiB that each GPU holds for
+ * the life of the process; host data reaches it through the arguments of
+ * small copy kernels, so a caller's own capture keeps a copy of it.  A run
+ * needing more than 8 MiB there (about 9 bytes per step per scaled source,
+ * plus about 40 bytes per source and receiver and 4 per xy tile) fails with
+ * STENCIL_E_NOMEM before any device work.  The temporally blocked variants
+ * still take the workspace attached with stencil_set_workspace (caller
+ * memory).  Every call on one GPU shares that array: calls that may overlap
+ * in time on one GPU (different streams, or host threads) race and must
+ * not be issued; calls in order on one stream are safe.  Host memory is
+ * used to build the tables. */
+stencil_status stencil_run_noalloc(stencil_plan plan, void** fields, int64_t nsteps, const stencil_source* src,
+                                   const stencil_receivers* rec, void* stream);
+
 /* Absorbing layer for a wave plan (the boundary conditions Devito's
  * front end provides, Section 5.1): the sweep becomes the damped leapfrog
  *     u^{t+1} = (2u^t - (1 - g) u^{t-1} + beta .* L u^t) / (1 + g)

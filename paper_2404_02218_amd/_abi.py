@@ -81,7 +81,7 @@ CHECK_NONFINITE, CHECK_OVERFLOW, CHECK_UNSTABLE, CHECK_BAD_BETA = 1, 2, 4, 8
 
 
 EXPORTS = [
-    "stencil_create", "stencil_destroy", "stencil_layout", "stencil_apply", "stencil_run",
+    "stencil_create", "stencil_destroy", "stencil_layout", "stencil_apply", "stencil_run", "stencil_run_noalloc",
     "stencil_run_interp", "stencil_interp_weights", "stencil_wave_damping",
     "stencil_exchanges", "stencil_exchanges_box", "stencil_halo_pack", "stencil_halo_unpack",
     "stencil_program_create", "stencil_program_apply", "stencil_program_halo_dirs", "stencil_schedule",
@@ -121,6 +121,7 @@ def lib():
         "stencil_layout": [P, P, P, P, P],
         "stencil_apply": [P, P, P, P, P, P],
         "stencil_run": [P, P, I64, P, P, P],
+        "stencil_run_noalloc": [P, P, I64, P, P, P],
         "stencil_run_interp": [P, P, I64, P, P, P],
         "stencil_interp_weights": [P, I64, P, P, P],
         "stencil_wave_damping": [P, P],

@@ -798,6 +798,90 @@ bool graphs_enabled() {
 
 }  // namespace
 
+// ------------------------------------------------------- allocation-free run
+// The device memory stencil_run_noalloc works in: the point tables of a run
+// and the formed source amounts.  Each GPU holds its own copy for the life
+// of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name is a host
+// stand-in).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> the array's address there
+
+// the array's address on the current device, looked up once per device
+stencil_status noalloc_scratch(void*& ptr) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return fail(STENCIL_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, q).first;
+    }
+    ptr = it->second;
+    return STENCIL_OK;
+}
+
+// Consecutive 256-byte aligned regions of the scratch array (base 0: only
+// count the bytes).
+struct ScratchCursor {
+    uintptr_t base;
+    size_t used = 0;
+    char* take(size_t bytes) {
+        const uintptr_t p = base + used;
+        used += (bytes + 255) / 256 * 256;
+        return (char*)p;
+    }
+};
+
+// Device copies of one host point list in the scratch array: element
+// offsets, position groups and (if tiled) the tile CSR.
+struct ScratchPoints {
+    char *off = nullptr, *grp = nullptr, *gbeg = nullptr, *zyx4 = nullptr, *tiles = nullptr;
+};
+
+void place_points(ScratchCursor& c, const HostPoints& H, ScratchPoints& P) {
+    P.off = c.take(sizeof(int64_t) * H.off.size());
+    P.grp = c.take(sizeof(int) * H.grp.size());
+    P.gbeg = c.take(sizeof(int) * H.gbeg.size());
+    if (H.tiled) {
+        P.zyx4 = c.take(sizeof(int) * H.zyx4.size());
+        P.tiles = c.take(sizeof(int) * H.tiles.size());
+    }
+}
+
+hipError_t fill_points(const HostPoints& H, const ScratchPoints& P, hipStream_t s) {
+    hipError_t e = launch_fill_words(P.off, H.off.data(), sizeof(int64_t) * H.off.size(), s);
+    if (e == hipSuccess) e = launch_fill_words(P.grp, H.grp.data(), sizeof(int) * H.grp.size(), s);
+    if (e == hipSuccess) e = launch_fill_words(P.gbeg, H.gbeg.data(), sizeof(int) * H.gbeg.size(), s);
+    if (e == hipSuccess && H.tiled) e = launch_fill_words(P.zyx4, H.zyx4.data(), sizeof(int) * H.zyx4.size(), s);
+    if (e == hipSuccess && H.tiled) e = launch_fill_words(P.tiles, H.tiles.data(), sizeof(int) * H.tiles.size(), s);
+    return e;
+}
+
+SrcList scratch_src_list(const HostPoints& H, const ScratchPoints& P, const double* amp) {
+    SrcList l{};
+    l.n = H.n;
+    l.zyx4 = (const int*)P.zyx4;
+    l.tile_begin = (const int*)P.tiles;
+    l.off = (const int64_t*)P.off;
+    l.amp = amp;
+    l.scale = nullptr;
+    l.ngrp = H.ngrp;
+    l.grp = (const int*)P.grp;
+    l.gbeg = (const int*)P.gbeg;
+    return l;
+}
+
+}  // namespace
+
 // ======================================================================== C ABI
 extern "C" {
 
@@ -1044,6 +1128,60 @@ static stencil_status run_common(stencil_plan p, void** fields, int64_t nsteps, 
     } else {
         ST_TRY(enqueue_run(p, a, b, beta, nsteps, plan_lists(p, src, rec), s));
     }
+    if (nsteps & 1) std::swap(fields[0], fields[1]);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_run_noalloc(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                                   const stencil_receivers* rec, void* stream) {
+    ST_TRY(check_sweep_plan(p));
+    ST_TRY(run_args(p, fields, nsteps, src, rec));
+    ST_TRY(check_source_scale(src));
+    ST_TRY(check_workspace(p));
+    const Layout& L = p->L;
+    const Variant var = variant_of(p->variant);
+    const int cfg = (var.zmarch || var.tb) ? var.cfg : -1;
+    const int64_t ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+    HostPoints hs, he, hr;
+    host_points(L, ns, ns ? src->pos : nullptr, cfg, hs);
+    if (var.tb) host_points(L, ns, ns ? src->pos : nullptr, var.cfg, he, 4);
+    host_points(L, nr, nr ? rec->pos : nullptr, -1, hr);
+    const bool scaled = ns > 0 && src->scale;
+    // the regions this run needs, laid out from offset 0 first to size them
+    ScratchCursor sizing{0};
+    ScratchPoints ps, pe, pr;
+    place_points(sizing, hs, ps);
+    if (var.tb) place_points(sizing, he, pe);
+    place_points(sizing, hr, pr);
+    if (scaled) sizing.take(sizeof(double) * (size_t)(nsteps * ns));
+    if (sizing.used > kNoAllocScratchBytes)
+        return fail(STENCIL_E_NOMEM, "this run needs " + std::to_string(sizing.used) +
+                                         " bytes of the static scratch; its maximum is " +
+                                         std::to_string(kNoAllocScratchBytes) +
+                                         " (fewer sources/receivers or steps per call, or stencil_run)");
+    void* base = nullptr;
+    ST_TRY(noalloc_scratch(base));
+    ScratchCursor cur{(uintptr_t)base};
+    place_points(cur, hs, ps);
+    if (var.tb) place_points(cur, he, pe);
+    place_points(cur, hr, pr);
+    double* amounts = scaled ? (double*)cur.take(sizeof(double) * (size_t)(nsteps * ns)) : nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(fill_points(hs, ps, s));
+    if (var.tb) HIP_TRY(fill_points(he, pe, s));
+    HIP_TRY(fill_points(hr, pr, s));
+    const double* amp = ns ? src->amp : nullptr;
+    if (scaled) {
+        HIP_TRY(launch_spread(src->amp, src->scale, 0, ns, nsteps, amounts, s));
+        amp = amounts;
+    }
+    RunLists RL;
+    RL.st = scratch_src_list(hs, ps, amp);
+    RL.se = var.tb ? scratch_src_list(he, pe, amp) : SrcList{};
+    RL.rl.n = hr.n;
+    RL.rl.off = (const int64_t*)pr.off;
+    RL.rl.trace = nr ? rec->trace : nullptr;
+    ST_TRY(enqueue_run(p, fields[0], fields[1], p->kind == STENCIL_WAVE2 ? fields[2] : nullptr, nsteps, RL, s));
     if (nsteps & 1) std::swap(fields[0], fields[1]);
     return STENCIL_OK;
 }
