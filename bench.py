@@ -297,7 +297,9 @@ def host_cpu():
 
 
 def bench_batch(S, W, steps):
-    """32 uneven shots: one batched graph vs 32 sequential plain runs."""
+    """32 uneven shots in one graph (the tuned batch variant: fused launches
+    over all shots, or every shot with its own tuned plan in four concurrent
+    branches) vs 32 sequential tuned runs."""
     import torch
     B = W.batch_c4()
     shapes = [s.shape for s in B.shots]
@@ -322,6 +324,20 @@ def bench_batch(S, W, steps):
         for _ in range(steps):
             run_batch()
     ms_b = t.ms / steps
+    tuned = bp.variant
+    # whole runs of the other candidate forms, for the record
+    names = {bp.variant_name(v): v for v in range(1, bp.variant_count())}
+    per_variant = {bp.variant_name(tuned): round(ms_b, 2)}
+    for name in ("shots_concurrent_4", "tb2_64x32_t768_zc128", "tb2_64x32_t768_zc256", "zmarch_64x16_t256_zc32_nt",
+                 "zmarch_64x16_t256_zc128_nt", "zmarch_64x16_t256_zc256_nt"):
+        if name in names and name not in per_variant:
+            bp.variant = names[name]
+            run_batch()
+            with Timer() as t:
+                for _ in range(steps):
+                    run_batch()
+            per_variant[name] = round(t.ms / steps, 2)
+    bp.variant = tuned
     # sequential plain runs on the same fields' data
     plans = []
     for i, sh in enumerate(B.shots):
@@ -350,7 +366,7 @@ def bench_batch(S, W, steps):
             "ms_per_run": round(ms_b, 2), "sequential_GPts_s": round(pts / (ms_s * 1e-3) / 1e9, 2),
             "sequential_ms": round(ms_s, 2), "batched_vs_sequential": round(ms_s / ms_b, 3),
             "bitwise_equal_to_sequential": bool(same),
-            "variant": bp.variant_name(bp.variant),
+            "variant": bp.variant_name(bp.variant), "ms_per_run_by_variant": per_variant,
             "sequential_variants": sorted({p.variant_name(p.variant) for p, _ in plans})}
 
 

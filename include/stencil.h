@@ -571,8 +571,12 @@ stencil_status stencil_check(stencil_plan plan, void* const* fields, stencil_che
  * file path the cache is read from that file on the first tuning of the
  * process and every new choice is appended to it ("<arch> <key> <name>" per
  * line); a cached name the plan does not offer is ignored and re-tuned.  With
- * STENCIL_FORCE_VARIANT set to a variant name that the plan offers, tuning
- * picks that variant without timing.  For a program plan `fields`
+ * STENCIL_FORCE_VARIANT set to a comma-separated list of variant names,
+ * tuning picks the first one the plan offers without timing.  A batch plan's
+ * last variant, "shots_concurrent_4", runs every shot with its own plan
+ * (tuned with the batch, so each shot gets its own fastest variant) and
+ * spreads the shots over four streams forked from and joined back to the
+ * caller's stream, captured in one graph.  For a program plan `fields`
  * holds its nin input pointers, then its nout output pointers: the compiled
  * variants (0, 2 and 3 where it exists) are applied to them, the fastest
  * is kept, and the outputs hold the program's result (not cached; the

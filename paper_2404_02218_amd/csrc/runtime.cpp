@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -164,6 +165,9 @@ struct Variant {
 };
 
 constexpr int kNumZVariants = kNumTileCfgs * kNumZChunks;
+// branches of the concurrent batch variant: the hardware queues a process
+// gets by default
+constexpr int kBranches = 4;
 
 Variant variant_of(int v) {
     Variant r;
@@ -283,6 +287,12 @@ struct stencil_plan_s {
     // field pair of every shot, and the view tables of even and odd passes
     std::vector<PointTables> shot_src_ext;
     DevTable tbviews[2];
+    // batch, concurrent variant: one sweep plan per shot with its own tuned
+    // variant; the shots' runs go to kBranches streams, forked from and
+    // joined back to the caller's stream (in one graph)
+    std::vector<stencil_plan_s*> shot_plans;
+    hipStream_t branch[kBranches] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {};
     // stencil program
     int nin = 0, nout = 0, reach[3] = {0, 0, 0};
     std::vector<ProgTerm> pterms;
@@ -293,6 +303,12 @@ struct stencil_plan_s {
     ~stencil_plan_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap) (void)hipStreamDestroy(cap);
+        for (stencil_plan_s* q : shot_plans) delete q;
+        for (hipStream_t b : branch)
+            if (b) (void)hipStreamDestroy(b);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        for (hipEvent_t e : join_ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -331,10 +347,15 @@ bool heat2d_supported(const stencil_plan_s* p) {
 int variant_count_of(const stencil_plan_s* p) {
     if (p->program)
         return 3 + (program_rtc_lds_bytes(p->nin, p->reach[0], p->reach[1], false, 2 * kProgTileY) <= kLdsPerCu);
-    if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0);
+    // batch: z-marching and temporally blocked launches over all shots, then
+    // the concurrent per-shot runs
+    if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0) + 1;
     if (p->ndim != 3) return heat2d_supported(p) ? 1 + kNumHeat2dCfgs : 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
 }
+
+// the batch variant that runs every shot with its own plan, concurrently
+bool batch_concurrent(const stencil_plan_s* p, int v) { return p->batch && v == variant_count_of(p) - 1; }
 
 // plans of the sweep entry points (not stencil programs)
 stencil_status check_sweep_plan(stencil_plan p) {
@@ -498,6 +519,31 @@ void set_tiling(ZView& v, const Layout& L, const Variant& var) {
     v.nty = (L.g.n[1] + TY - 1) / TY;
     chunking(L.g.n[0], var.zc, v.zc, v.nzc);
     if (L.g.n[0] == 0 || L.g.n[1] == 0 || L.g.n[2] == 0) v.ntx = v.nty = v.nzc = 0;
+}
+
+// Per-shot z-chunk lengths of a fused batch launch: the smallest shots,
+// together at most 30% of the points, take 32-plane chunks and the others
+// the variant's chunk length.  The block map puts the largest (shot, chunk)
+// groups first on every XCD, so each launch ends with short workgroups that
+// fill the compute units the long ones leave idle, while the large shots
+// keep long chunks (fewer warm-up planes).
+std::vector<int> batch_chunks(const std::vector<Layout>& shots, int zc) {
+    const int ns = (int)shots.size();
+    std::vector<int> out(ns, zc), order(ns);
+    int64_t total = 0;
+    for (int i = 0; i < ns; i++) {
+        order[i] = i;
+        total += (int64_t)shots[i].g.n[0] * shots[i].g.n[1] * shots[i].g.n[2];
+    }
+    auto pts = [&](int i) { return (int64_t)shots[i].g.n[0] * shots[i].g.n[1] * shots[i].g.n[2]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pts(a) < pts(b); });
+    int64_t acc = 0;
+    for (int i : order) {
+        acc += pts(i);
+        if (10 * acc > 3 * total) break;
+        out[i] = std::min(zc, 32);
+    }
+    return out;
 }
 
 // Copy list of the periodic self-exchange: each receive box takes the send
@@ -1023,6 +1069,12 @@ static stencil_status prepare_points(stencil_plan p, const stencil_source* src, 
 // workspace bytes the plan's current variant needs: the second field pair
 // of the temporally blocked wave sweep (one pair per shot for a batch)
 static size_t run_workspace_bytes(const stencil_plan_s* p) {
+    if (batch_concurrent(p, p->variant)) {
+        // the shots whose own plan runs the temporally blocked sweep
+        size_t b = 0;
+        for (const stencil_plan_s* q : p->shot_plans) b += run_workspace_bytes(q);
+        return b;
+    }
     const Variant var = variant_of(p->variant);
     if (!var.tb) return 0;
     if (p->batch) {
@@ -1712,6 +1764,7 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
     const int ns = (int)p->shots.size();
     views.assign(ns, ZView{});
     p->bstart.assign(ns + 1, 0);
+    const std::vector<int> zcs = batch_chunks(p->shots, var.zc);
     for (int s = 0; s < ns; s++) {
         const Layout& L = p->shots[s];
         ZView& v = views[s];
@@ -1720,7 +1773,9 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
         v.out = fields[3 * s + 1];
         v.beta = fields[3 * s + 2];
         v.g = L.g;
-        set_tiling(v, L, var);
+        Variant vs = var;
+        vs.zc = zcs[s];
+        set_tiling(v, L, vs);
         const stencil_source* ss = src ? &src[s] : nullptr;
         const stencil_receivers* rr = rec ? &rec[s] : nullptr;
         ST_TRY(build_points(L, ss ? ss->n : 0, ss ? ss->pos : nullptr, var.cfg, p->shot_src[s]));
@@ -1813,6 +1868,145 @@ static stencil_status enqueue_batch(stencil_plan p, const std::vector<ZView>& vi
     return STENCIL_OK;
 }
 
+// The concurrent batch variant's per-shot plans (created on first use with
+// their default variant) and branch streams (default priority) and events.
+static stencil_status ensure_shot_plans(stencil_plan p) {
+    if (p->shot_plans.size() == p->shots.size()) return STENCIL_OK;
+    for (size_t sh = p->shot_plans.size(); sh < p->shots.size(); sh++) {
+        const Grid3& g = p->shots[sh].g;
+        const int64_t shape[3] = {g.n[0], g.n[1], g.n[2]};
+        stencil_plan q = nullptr;
+        ST_TRY(stencil_create(&q, STENCIL_WAVE2, 3, shape, p->radius, p->coeffs, p->halo, (stencil_dtype)p->dtype,
+                              STENCIL_BC_DIRICHLET0));
+        p->shot_plans.push_back(q);
+    }
+    return STENCIL_OK;
+}
+
+static stencil_status ensure_branches(stencil_plan p) {
+    for (hipStream_t& b : p->branch)
+        if (!b) HIP_TRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    if (!p->fork_ev) HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+    for (hipEvent_t& e : p->join_ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return STENCIL_OK;
+}
+
+// shots to branches, largest first, each to the branch with the least work
+static std::vector<std::vector<int>> branch_lists(const stencil_plan_s* p) {
+    const int ns = (int)p->shots.size();
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; i++) order[i] = i;
+    auto work = [&](int i) {
+        const Grid3& g = p->shots[i].g;
+        return (int64_t)g.n[0] * g.n[1] * g.n[2];
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<std::vector<int>> lists(kBranches);
+    std::vector<int64_t> load(kBranches, 0);
+    for (int i : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += work(i);
+        lists[b].push_back(i);
+    }
+    return lists;
+}
+
+// fork from `main` to the branches, run `body(branch, shot)` for each shot of
+// each branch, join back
+static stencil_status fork_join(stencil_plan p, hipStream_t main, const std::vector<std::vector<int>>& lists,
+                                const std::function<stencil_status(hipStream_t, int)>& body) {
+    HIP_TRY(hipEventRecord(p->fork_ev, main));
+    for (int b = 0; b < kBranches; b++) HIP_TRY(hipStreamWaitEvent(p->branch[b], p->fork_ev, 0));
+    for (int b = 0; b < kBranches; b++)
+        for (int sh : lists[b]) ST_TRY(body(p->branch[b], sh));
+    for (int b = 0; b < kBranches; b++) {
+        HIP_TRY(hipEventRecord(p->join_ev[b], p->branch[b]));
+        HIP_TRY(hipStreamWaitEvent(main, p->join_ev[b], 0));
+    }
+    return STENCIL_OK;
+}
+
+// Every shot's whole run with its own plan (its tuned variant, tables and
+// workspace slice), the shots spread over kBranches streams so that their
+// kernels overlap where one alone leaves compute units idle.  Arguments are
+// validated by the caller.
+static stencil_status batch_run_concurrent(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
+                                           const stencil_receivers* rec, hipStream_t s) {
+    ST_TRY(ensure_shot_plans(p));
+    ST_TRY(ensure_branches(p));
+    const int ns = (int)p->shots.size();
+    std::vector<stencil_source> scaled(ns);
+    std::vector<RunLists> lists(ns);
+    char* wsp = (char*)p->ws;
+    for (int sh = 0; sh < ns; sh++) {
+        stencil_plan q = p->shot_plans[sh];
+        const size_t need = run_workspace_bytes(q);
+        q->ws = need ? wsp : nullptr;
+        q->ws_bytes = need;
+        wsp += need;
+        const stencil_source* ss = src ? &src[sh] : nullptr;
+        const stencil_receivers* rr = rec ? &rec[sh] : nullptr;
+        ST_TRY(prepare_points(q, ss, rr));
+        const stencil_source* use = ss;
+        ST_TRY(scaled_source(q->amp_scaled, ss, nsteps, scaled[sh], use, s));
+        lists[sh] = plan_lists(q, use, rr);
+    }
+    const std::vector<std::vector<int>> bl = branch_lists(p);
+    auto body = [&](hipStream_t bs, int sh) -> stencil_status {
+        return enqueue_run(p->shot_plans[sh], fields[3 * sh], fields[3 * sh + 1], fields[3 * sh + 2], nsteps, lists[sh],
+                           bs);
+    };
+    if (nsteps >= 2 && graphs_enabled()) {
+        std::vector<int64_t> key = {nsteps, p->variant, -1};
+        for (int sh = 0; sh < ns; sh++) {
+            const stencil_plan_s* q = p->shot_plans[sh];
+            const RunLists& L = lists[sh];
+            for (const void* ptr : {(const void*)fields[3 * sh], (const void*)fields[3 * sh + 1],
+                                    (const void*)fields[3 * sh + 2], (const void*)q->ws, (const void*)L.st.zyx4,
+                                    (const void*)L.st.tile_begin, (const void*)L.st.off, (const void*)L.st.amp,
+                                    (const void*)L.st.grp, (const void*)L.st.gbeg, (const void*)L.se.zyx4,
+                                    (const void*)L.se.tile_begin, (const void*)L.rl.off, (const void*)L.rl.trace})
+                key.push_back((int64_t)(uintptr_t)ptr);
+            key.push_back(q->variant);
+            key.push_back(L.st.n);
+            key.push_back(L.st.ngrp);
+            key.push_back(L.se.n);
+            key.push_back(L.rl.n);
+        }
+        if (!p->gexec || key != p->gkey) {
+            if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+            if (p->gexec) {
+                HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(hipGraphExecDestroy(p->gexec));
+                p->gexec = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            stencil_status st = fork_join(p, p->cap, bl, body);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap, &graph);
+            if (st != STENCIL_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(STENCIL_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                p->gexec = nullptr;
+                return fail(STENCIL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            p->gkey = key;
+        }
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+    } else {
+        ST_TRY(fork_join(p, s, bl, body));
+    }
+    if (nsteps & 1)
+        for (int sh = 0; sh < ns; sh++) std::swap(fields[3 * sh], fields[3 * sh + 1]);
+    return STENCIL_OK;
+}
+
 stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
                                  const stencil_receivers* rec, void* stream) {
     ST_TRY(check_plan(p, true));
@@ -1836,8 +2030,9 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
         }
     }
     ST_TRY(check_workspace(p));
-    const Variant var = variant_of(p->variant);
     hipStream_t s = (hipStream_t)stream;
+    if (batch_concurrent(p, p->variant)) return batch_run_concurrent(p, fields, nsteps, src, rec, s);
+    const Variant var = variant_of(p->variant);
     // shots whose sources carry per-point scales use their formed amounts
     std::vector<stencil_source> srcs;
     if (src) {
@@ -2308,6 +2503,8 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
                                   std::to_string(32 * kProgTileY)
                             : (variant == 0 ? "program_rtc_" : variant == 1 ? "program_interp_" : "program_rtc_tight_") +
                                   tile;
+    } else if (batch_concurrent(p, variant)) {
+        name = "shots_concurrent_" + std::to_string(kBranches);
     } else if (p->ndim == 2 && variant > 0) {
         const Heat2dCfg& c = kHeat2dCfgs[variant - 1];
         name = "tb2d_t" + std::to_string(c.t) + "_" + std::to_string(c.tx) + "x" + std::to_string(c.ty);
@@ -2433,6 +2630,76 @@ static stencil_status time_heat2d_graph(stencil_plan p, int var, const void* in,
     return STENCIL_OK;
 }
 
+// The concurrent batch variant as a tuning candidate: each shot's own plan
+// is tuned on its fields first (cached per shape); then every shot's kernel
+// advances two steps (one temporally blocked launch, or two single-step
+// launches) into scratch outputs, in the branches from fork to join, `reps`
+// times.  scratch holds two fields per shot.  Result: ms per step.
+static stencil_status time_batch_concurrent(stencil_plan p, void* const* fields, int reps, void* scratch, hipStream_t s,
+                                            hipEvent_t e0, hipEvent_t e1, float& ms_per_step) {
+    ST_TRY(ensure_shot_plans(p));
+    ST_TRY(ensure_branches(p));
+    const int ns = (int)p->shots.size();
+    for (int sh = 0; sh < ns; sh++) ST_TRY(stencil_tune(p->shot_plans[sh], fields + 3 * sh, reps, s));
+    std::vector<int64_t> off(ns);
+    int64_t o = 0;
+    for (int sh = 0; sh < ns; sh++) {
+        off[sh] = o;
+        o += 2 * round_up(p->shots[sh].bytes, 256);
+    }
+    const std::vector<std::vector<int>> bl = branch_lists(p);
+    auto body = [&](hipStream_t bs, int sh) -> stencil_status {
+        const stencil_plan_s* q = p->shot_plans[sh];
+        const Layout& L = q->L;
+        const Variant var = variant_of(q->variant);
+        char* out = (char*)scratch + off[sh];
+        if (var.tb) {
+            TBView t{};
+            t.u = fields[3 * sh];
+            t.prev = fields[3 * sh + 1];
+            t.beta = fields[3 * sh + 2];
+            t.out1 = out;
+            t.out2 = out + round_up(L.bytes, 256);
+            t.g = L.g;
+            t.ntx = (L.g.n[2] + kTB2TileX - 1) / kTB2TileX;
+            t.nty = (L.g.n[1] + kTB2TileY - 1) / kTB2TileY;
+            chunking(L.g.n[0], var.zc, t.zc, t.nzc);
+            t.range = (uint32_t)L.bytes;
+            HIP_TRY(launch_tb2(MODE_WAVE, q->radius, q->dtype, t, q->w, 0, -1, -1, bs));
+            return STENCIL_OK;
+        }
+        for (int k = 0; k < 2; k++) {
+            ZView v{};
+            v.u = fields[3 * sh];
+            v.prev = fields[3 * sh + 1];
+            v.beta = fields[3 * sh + 2];
+            v.out = out;
+            v.g = L.g;
+            if (var.zmarch) {
+                set_tiling(v, L, var);
+                HIP_TRY(launch_zmarch(MODE_WAVE, q->radius, q->dtype, var.cfg, v, q->w, 0, 0, -1, bs));
+            } else {
+                Box3 box{};
+                for (int a = 0; a < 3; a++) {
+                    box.lo[a] = 0;
+                    box.n[a] = L.g.n[a];
+                }
+                HIP_TRY(launch_point(MODE_WAVE, q->radius, q->dtype, v, q->w, box, bs));
+            }
+        }
+        return STENCIL_OK;
+    };
+    ST_TRY(fork_join(p, s, bl, body));   // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; r++) ST_TRY(fork_join(p, s, bl, body));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ms_per_step = ms / (2.0f * (float)reps);
+    return STENCIL_OK;
+}
+
 // Program plans: fields = the nin inputs, then the nout outputs.  Each
 // compiled variant (0, 2 and, where it exists, 3) is applied once untimed
 // (that compiles and loads it) and then `reps` times on the caller's fields;
@@ -2488,25 +2755,41 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     if (p->program) return tune_program(p, fields, reps, stream);
     int nvar = 0;
     ST_TRY(stencil_variant_count(p, &nvar));
+    // the concurrent batch variant runs each shot with its own tuned plan
+    auto tune_shot_plans = [&]() -> stencil_status {
+        if (!batch_concurrent(p, p->variant)) return STENCIL_OK;
+        ST_TRY(ensure_shot_plans(p));
+        for (size_t sh = 0; sh < p->shots.size(); sh++) ST_TRY(stencil_tune(p->shot_plans[sh], fields + 3 * sh, reps, stream));
+        return STENCIL_OK;
+    };
     if (const char* force = std::getenv("STENCIL_FORCE_VARIANT")) {
-        const int v = variant_by_name(p, force);
-        if (v >= 0) {
-            p->variant = v;
-            return STENCIL_OK;
+        // a comma-separated list: the first name this plan offers wins
+        std::string list(force);
+        size_t at = 0;
+        while (at <= list.size()) {
+            const size_t end = std::min(list.find(',', at), list.size());
+            const int v = variant_by_name(p, list.substr(at, end - at));
+            if (v >= 0) {
+                p->variant = v;
+                return tune_shot_plans();
+            }
+            at = end + 1;
         }
     }
     const std::string key = tune_key(p);
+    std::string cached;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            // a cached name this plan does not offer is ignored and re-tuned
-            const int v = variant_by_name(p, it->second);
-            if (v >= 0) {
-                p->variant = v;
-                return STENCIL_OK;
-            }
+        if (it != g_tune_cache.end()) cached = it->second;
+    }
+    if (!cached.empty()) {
+        // a cached name this plan does not offer is ignored and re-tuned
+        const int v = variant_by_name(p, cached);
+        if (v >= 0) {
+            p->variant = v;
+            return tune_shot_plans();
         }
     }
     if (nvar <= 1) return STENCIL_OK;
@@ -2536,6 +2819,15 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     stencil_status st = STENCIL_OK;
     DevTable vt, bs, tvt;
     for (int var_i = p->batch ? 1 : 0; var_i < nvar && st == STENCIL_OK; var_i++) {
+        if (batch_concurrent(p, var_i)) {
+            float ms = 0;
+            st = time_batch_concurrent(p, fields, reps, scratch, s, e0, e1, ms);
+            if (st == STENCIL_OK && ms < best_ms) {
+                best_ms = ms;
+                best = var_i;
+            }
+            continue;
+        }
         if (heat2d_supported(p)) {
             float ms = 0;
             st = time_heat2d_graph(p, var_i, fields[0], scratch, (char*)scratch + round_up(p->L.bytes, 256), reps, s,
@@ -2550,6 +2842,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
         std::vector<ZView> views;
         std::vector<int> bst(1, 0);
         int64_t off = 0;
+        const std::vector<int> zcs = p->batch ? batch_chunks(p->shots, var.zc) : std::vector<int>(1, var.zc);
         for (size_t i = 0; i < Ls.size(); i++) {
             const Layout& L = *Ls[i];
             ZView v{};
@@ -2560,7 +2853,9 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             v.out = (char*)scratch + off;
             off += round_up(L.bytes, 256);
             v.g = L.g;
-            if (var.zmarch || var.tb) set_tiling(v, L, var);
+            Variant vs = var;
+            vs.zc = zcs[i];
+            if (var.zmarch || var.tb) set_tiling(v, L, vs);
             views.push_back(v);
             bst.push_back(bst.back() + (int)zmarch_blocks(v));
         }

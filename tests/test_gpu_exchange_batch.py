@@ -107,6 +107,8 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
     bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8), dtype=dtype)
     tb = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("tb2_")]
     assert len(tb) == 3
+    conc = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("shots_concurrent")]
+    assert len(conc) == 1
     fields, srcs, amps, recs, trs, ins = [], [], [], [], [], []
     for i, sh in enumerate(shapes):
         u0, um1, beta = wave_inputs(sh, seed=100 + i, dtype=dtype)
@@ -119,7 +121,7 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
         amps.append(torch_f64(np.random.default_rng(200 + i).standard_normal((steps, 1)), device))
         recs.append(np.array([[1, 2, 3], [s - 1 for s in sh]][: 1 + i % 2]))
         trs.append(torch.zeros((steps, len(recs[-1])), dtype=torch.float64, device=device))
-    for v in (1, 5, 9, *tb):
+    for v in (1, 5, 9, *tb, *conc):
         bp.variant = v
         for i in range(len(shapes)):
             for fld, a in zip(fields[i], ins[i]):
@@ -133,6 +135,57 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
             assert np.array_equal(fields[i][0].interior(4), a), (v, i)
             assert np.array_equal(fields[i][1].interior(4), b), (v, i)
             assert np.array_equal(trs[i].cpu().numpy(), tr), (v, i)
+
+
+def test_concurrent_batch_with_tuned_shot_plans(device, monkeypatch):
+    """The concurrent batch variant forced through the environment: tuning
+    then tunes each shot's own plan (forced to the temporally blocked sweep,
+    each taking a slice of the batch's workspace), and two runs in a row (the
+    second replays the captured graph of four branches) give every shot the
+    bits of its own sequential run."""
+    import torch
+    # the batch takes the concurrent variant, and every shot's own plan the
+    # temporally blocked sweep (a slice of the batch's workspace each)
+    monkeypatch.setenv("STENCIL_FORCE_VARIANT", "shots_concurrent_4,tb2_64x32_t768_zc64")
+    shapes = [(64, 64, 64), (20, 33, 45), (48, 100, 70), (9, 40, 12), (33, 70, 130), (16, 16, 16)]
+    bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
+    steps = 12
+    fields, srcs, amps, recs, trs, ins = [], [], [], [], [], []
+    for i, sh in enumerate(shapes):
+        u0, um1, beta = wave_inputs(sh, seed=150 + i)
+        ins.append((u0, um1, beta))
+        f = [bp.field(i) for _ in range(3)]
+        for fld, a in zip(f, (u0, um1, beta)):
+            fld.load(W.embed(a, 4))
+        fields.append(f)
+        srcs.append(np.array([[s // 2 for s in sh], [1, 1, 1]]))
+        amps.append(torch_f64(np.random.default_rng(250 + i).standard_normal((steps, 2)), device))
+        recs.append(np.array([[s - 2 for s in sh]]))
+        trs.append(torch.zeros((steps, 1), dtype=torch.float64, device=device))
+    bp.tune(fields, reps=1)
+    assert bp.variant_name(bp.variant) == "shots_concurrent_4"
+    fb = [(bp.layouts[i].bytes + 255) // 256 * 256 for i in range(len(shapes))]
+    from paper_2404_02218_amd import _abi
+    import ctypes as C
+    need = C.c_size_t()
+    _abi.call("stencil_run_workspace", bp._h, C.byref(need))
+    assert need.value == 2 * sum(fb)
+    refs = []
+    for i, sh in enumerate(shapes):
+        plan = S.Plan(S.WAVE2, sh, 4, S.second_derivative_weights(8), halo=4)
+        refs.append(gpu_wave(plan, *ins[i], steps, src=srcs[i], amp=amps[i].cpu().numpy(), rec=recs[i], variant=2))
+    for rep in range(2):
+        for i in range(len(shapes)):
+            for fld, a in zip(fields[i], ins[i]):
+                fld.load(W.embed(a, 4))
+            trs[i].zero_()
+        bp.run(fields, steps, srcs, amps, recs, trs)
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            a, b, tr = refs[i]
+            assert np.array_equal(fields[i][0].interior(4), a), (rep, i)
+            assert np.array_equal(fields[i][1].interior(4), b), (rep, i)
+            assert np.array_equal(trs[i].cpu().numpy(), tr), (rep, i)
 
 
 @pytest.mark.parametrize("dtype,name,bound", [(S.BF16, "bf16", 5e-2), (S.F16, "f16", 2e-2)])
