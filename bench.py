@@ -42,12 +42,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "GPts/s + % of HBM peak, 3D so-8 wave; batched & adjoint vs plain, same GPU"
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
-# the counters are tied to every source of the library (kernels and the
-# runtime that picks their launch shapes)
 CSRC = os.path.join(ROOT, "paper_2404_02218_amd", "csrc")
-# the device code (kernels and the headers they include); the host-only
-# runtime and program generator do not change what a kernel moves
-KERNEL_SOURCES = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+# the stored traffic is tied to the sources the headline's kernels compile
+# from: the translation units of the plain and temporally blocked FP32 sweeps
+# and every header they include (the host runtime and the other kernels do
+# not change what these kernels move)
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in
+                  ("zmarch_tb.hip", "zmarch_f32.hip", "zmarch_tb.hpp", "zmarch.hpp", "kernels.hpp", "device.hpp")]
 
 
 def log(*a):
@@ -75,6 +76,10 @@ def parse():
                     choices=["pw", "pw_loop", "slab", "faces", "absorbing", "heat2d", "batch", "adjoint",
                              "precision"],
                     help="run one secondary leg only and print its JSON (profiling)")
+    ap.add_argument("--batch-steps", type=int, default=200, help="leapfrog steps of the batched-shots leg")
+    ap.add_argument("--batch-variant", default=None,
+                    help="batched-shots leg: run this variant only (no tuning, no sequential runs; profiling)")
+    ap.add_argument("--adjoint-steps", type=int, default=500, help="leapfrog steps of the gradient leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (for counter scaling)")
     return ap.parse_args()
@@ -296,12 +301,12 @@ def host_cpu():
     return {"model": model, "sockets": len(sockets) or None, "affinity_cores": len(os.sched_getaffinity(0))}
 
 
-def bench_batch(S, W, steps):
+def bench_batch(S, W, steps, nsteps=200, only_variant=None):
     """32 uneven shots in one graph (the tuned batch variant: fused launches
     over all shots, or every shot with its own tuned plan in four concurrent
     branches) vs 32 sequential tuned runs."""
     import torch
-    B = W.batch_c4()
+    B = W.batch_c4(nsteps=nsteps)
     shapes = [s.shape for s in B.shots]
     bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
     fields, amps = [], []
@@ -311,6 +316,21 @@ def bench_batch(S, W, steps):
         fields.append(f)
         amps.append(torch.from_numpy(sh.src_amp).cuda())
     srcs = [sh.src for sh in B.shots]
+    if only_variant is not None:
+        bp.variant = {bp.variant_name(v): v for v in range(1, bp.variant_count())}[only_variant]
+        for f in fields:
+            f[0].storage.zero_()
+            f[1].storage.zero_()
+        bp.run(fields, B.nsteps, srcs, amps)
+        with Timer() as t:
+            for _ in range(steps):
+                for f in fields:
+                    f[0].storage.zero_()
+                    f[1].storage.zero_()
+                bp.run(fields, B.nsteps, srcs, amps)
+        pts = float(sum(np.prod(s) for s in shapes)) * B.nsteps
+        return {"variant": only_variant, "leapfrog_steps": B.nsteps, "ms_per_run": round(t.ms / steps, 3),
+                "GPts_s": round(pts / (t.ms / steps * 1e-3) / 1e9, 2)}
     bp.tune(fields, reps=2)
 
     def run_batch():
@@ -743,11 +763,11 @@ def bench_faces(S, W, reps=20):
     return out
 
 
-def bench_adjoint(S, W, steps):
+def bench_adjoint(S, W, steps, nsteps=500):
     """Checkpointed gradient of J = 1/2 |d|^2 (the adjoint's work does not
     depend on the residual values) vs the plain forward of the same model."""
     import torch
-    P = W.inversion_c5()
+    P = W.inversion_c5(nsteps=nsteps)
     n, N, k = P.shape[0], P.nsteps, P.checkpoint_every
     plan = S.Plan(S.WAVE2, P.shape, 4, S.second_derivative_weights(8), halo=4)
     f = [plan.field() for _ in range(3)]
@@ -817,10 +837,13 @@ def main():
                 "faces": lambda: bench_faces(S, W),
                 "absorbing": lambda: bench_absorbing(S, W, max(1, args.steps)),
                 "heat2d": lambda: bench_heat2d(S, W, max(1, args.steps)),
-                "batch": lambda: bench_batch(S, W, max(1, args.steps)),
-                "adjoint": lambda: bench_adjoint(S, W, max(1, args.steps)),
+                "batch": lambda: bench_batch(S, W, max(1, args.steps), args.batch_steps, args.batch_variant),
+                "adjoint": lambda: bench_adjoint(S, W, max(1, args.steps), args.adjoint_steps),
                 "precision": lambda: bench_precision(S, W)}
-        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        res = {args.leg: legs[args.leg]()}
+        if args.copy_calibration:
+            res["stream_copy_GBps"] = round(stream_copy_gbs(), 1)
+        print(json.dumps(res), flush=True)
         return
     if args.only_heat:
         out = {"heat3d_so4": bench_heat3d(S, W, args.steps, args.variant, args.heat_steps)}
