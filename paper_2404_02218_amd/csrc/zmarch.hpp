@@ -83,8 +83,10 @@ __device__ __forceinline__ void lds_put4(LdsT<T>* p, float4 v) {
     }
 }
 
-// Each thread owns VX consecutive x points (VX = 4 or 8) in VY rows strided
-// by BY; a row's VX values travel as VX/4 float4.
+// Each thread owns VX consecutive x points (VX = 4 or 8) in VY consecutive
+// rows (ty * VY .. ty * VY + VY - 1 of the tile), so the y taps of its rows
+// overlap and every tap row is read from LDS once; a row's VX values travel
+// as VX/4 float4.
 template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
 __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int lb, int parity, int arow,
                                             int trow, float* __restrict__ lds) {
@@ -127,14 +129,14 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     int64_t own[VY];
 #pragma unroll
     for (int j = 0; j < VY; j++) {
-        const int y = min(Y0 + ty + j * BY, ymax);
+        const int y = min(Y0 + ty * VY + j, ymax);
         own[j] = (int64_t)y * sy + min(X0 + VX * tx, xmaxv);
     }
     // absorbing layer: this thread's rows' and columns' damping profiles
     float dgy[VY], dgx[VX];
     if constexpr (MODE == MODE_WAVE_DAMP) {
 #pragma unroll
-        for (int j = 0; j < VY; j++) dgy[j] = v.damp[v.g.n[0] + min(Y0 + ty + j * BY, ny - 1)];
+        for (int j = 0; j < VY; j++) dgy[j] = v.damp[v.g.n[0] + min(Y0 + ty * VY + j, ny - 1)];
 #pragma unroll
         for (int i = 0; i < VX; i++) dgx[i] = v.damp[v.g.n[0] + ny + min(X0 + VX * tx + i, nx - 1)];
     }
@@ -200,7 +202,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     if constexpr (MODE == MODE_WAVE_ADJ) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            const int y = Y0 + ty + j * BY, x0 = X0 + VX * tx;
+            const int y = Y0 + ty * VY + j, x0 = X0 + VX * tx;
             dg_ok[j] = y < ny && x0 + VX - 1 < nx;
             dg_off[j] = v.g.origin + (int64_t)y * sy + x0;
             if (dg_ok[j] && zb < ze) {
@@ -247,7 +249,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         for (int j = 0; j < VY; j++)
 #pragma unroll
             for (int c = 0; c < NV; c++)
-                lds_put4<T>(&L[(R + ty + j * BY) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
+                lds_put4<T>(&L[(R + ty * VY + j) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
         if (z + R < ze) {
             LT* H = ldsT + hslot * PLANE;
 #pragma unroll
@@ -292,9 +294,22 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         if constexpr (MODE == MODE_WAVE_DAMP) dgz = v.damp[z];
         float o[VY][VX];
         float dv[VY][VX];
+        // y tap rows row0 - R .. row0 + VY - 1 + R of this thread's columns:
+        // its own rows from the z-queue, the 2R others from LDS, once each
+        const int row0 = R + ty * VY;
+        float4 yr[VY + 2 * R][NV];
+#pragma unroll
+        for (int q2 = 0; q2 < VY + 2 * R; q2++)
+#pragma unroll
+            for (int c = 0; c < NV; c++) {
+                if (q2 >= R && q2 < R + VY)
+                    yr[q2][c] = qi(R)[q2 - R][c];
+                else
+                    yr[q2][c] = lds_get4<T>(L + (row0 - R + q2) * LDX + 4 + VX * tx + 4 * c);
+            }
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            const int row = R + ty + j * BY;
+            const int row = row0 + j;
             const LT* Lr = L + row * LDX + VX * tx;
             // x taps: 4 left of the thread's points, its own VX, 4 right
             float xv[VX + 8];
@@ -317,8 +332,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             for (int k = 1; k <= R; k++)
 #pragma unroll
                 for (int c = 0; c < NV; c++) {
-                    ym[k - 1][c] = lds_get4<T>(L + (row - k) * LDX + 4 + VX * tx + 4 * c);
-                    yp[k - 1][c] = lds_get4<T>(L + (row + k) * LDX + 4 + VX * tx + 4 * c);
+                    ym[k - 1][c] = yr[R + j - k][c];
+                    yp[k - 1][c] = yr[R + j + k][c];
                 }
 #pragma unroll
             for (int i = 0; i < VX; i++) {
@@ -367,7 +382,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 for (int j = 0; j < VY; j++)
 #pragma unroll
                     for (int i = 0; i < VX; i++)
-                        if (dy == ty + j * BY && dx == VX * tx + i) {
+                        if (dy == ty * VY + j && dx == VX * tx + i) {
                             o[j][i] = inject<T>(o[j][i], amt);
                             if constexpr (MODE == MODE_WAVE_D) dv[j][i] = (float)((double)dv[j][i] + amt);
                         }
@@ -376,7 +391,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            const int y = Y0 + ty + j * BY;
+            const int y = Y0 + ty * VY + j;
             const int x0 = X0 + VX * tx;
             if (y < ny && x0 < nx) {
                 const int64_t off = (int64_t)z * sz + (int64_t)y * sy + x0;
