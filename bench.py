@@ -809,7 +809,9 @@ def bench_adjoint(S, W, steps, nsteps=500):
             "gradient_GPts_s": round(pts / (ms_g * 1e-3) / 1e9, 2), "gradient_ms": round(ms_g, 2),
             "gradient_vs_forward_time": round(ms_g / ms_f, 3),
             "workspace_GB": round(ws.numel() / 1e9, 2),
-            "bytes_per_gradient_update": 64,
+            # checkpointed forward 16 B, recompute with second differences
+            # 20 B, adjoint in pairs of steps 24 B (16 + 32 per pair)
+            "bytes_per_gradient_update": 60,
             "misfit": "J = 1/2 |d|^2 (d_obs = 0); timing only, parity is in the tests",
             "variant": plan.variant_name(plan.variant)}
 

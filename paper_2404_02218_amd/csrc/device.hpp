@@ -281,6 +281,7 @@ enum Mode : int {
     MODE_WAVE = 1,      // out = 2u - u_prev + beta L u
     MODE_WAVE_D = 2,    // as MODE_WAVE, also writes beta L u (+ source) to a second-difference field
     MODE_WAVE_ADJ = 3,  // as MODE_WAVE, then g += out * d for an imaging field pair (g, d)
+    MODE_WAVE_ADJ2 = 5, // as MODE_WAVE_ADJ, with g += u * d2 first: the input level paired with a second field d2
     MODE_WAVE_DAMP = 4, // the wave with an absorbing layer (damped_update), FP32
 };
 

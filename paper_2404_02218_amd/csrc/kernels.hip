@@ -253,7 +253,7 @@ hipError_t launch_point(int mode, int radius, int dtype, const ZView& v, const C
 
 hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& v, const Coefs& w, int parity,
                          int arow, int trow, hipStream_t s) {
-    if (mode == MODE_WAVE_D || mode == MODE_WAVE_ADJ || mode == MODE_WAVE_DAMP) {
+    if (mode == MODE_WAVE_D || mode == MODE_WAVE_ADJ || mode == MODE_WAVE_ADJ2 || mode == MODE_WAVE_DAMP) {
         // the adjoint path and the absorbing layer are FP32 only
         if (dtype != DT_F32) return hipErrorInvalidValue;
         return zmarch_adj_f32(mode, radius, cfg, v, w, parity, arow, trow, s);

@@ -58,7 +58,8 @@ struct ZView {
     const void* beta;   // wave only
     void* out;
     float* dfield;      // MODE_WAVE_D: written; MODE_WAVE_ADJ: read (same layout)
-    float* gfield;      // MODE_WAVE_ADJ: imaging partial (same layout)
+    float* gfield;      // MODE_WAVE_ADJ(2): imaging partial (same layout)
+    const float* dfield2;  // MODE_WAVE_ADJ2: the second difference paired with the input level u
     const float* damp;  // MODE_WAVE_DAMP: per-axis damping [n0 | n1 | n2], gamma = (d0 + d1) + d2
     Grid3 g;
     int ntx, nty, zc, nzc;  // z-marching tiling: tiles along x, y; z-chunk length and count

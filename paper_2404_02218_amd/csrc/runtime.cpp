@@ -2219,19 +2219,38 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
             v.src = fsrc;
             HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, (int)((t - c) & 1), (int)t, -1, s));
         }
-        for (int64_t kk = ce; kk > c; kk--) {
+        // Adjoint step kk produces lambda at level kk-1 and images it with
+        // the second difference of that level.  Steps go in pairs: a plain
+        // step (no imaging), then a step that images both its input level
+        // and its output, so the partial G is read and written once per two
+        // steps with the same roundings in the same order.  An odd remainder
+        // takes the one-level imaging step.
+        for (int64_t kk = ce; kk > c;) {
             ZView v{};
             v.u = L0;
             v.prev = L1;
             v.out = L1;
             v.beta = beta;
             v.g = L.g;
-            v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 1 - c));
-            v.gfield = G;
             set_tiling(v, L, var);
             v.src = asrc;
-            HIP_TRY(launch_zmarch(MODE_WAVE_ADJ, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 1), -1, s));
-            j++;
+            if (kk - 1 > c) {
+                HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 1), -1, s));
+                j++;
+                v.dfield2 = (const float*)slot(ws, A, A.seg0 + (kk - 1 - c));
+                v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 2 - c));
+                v.gfield = G;
+                HIP_TRY(launch_zmarch(MODE_WAVE_ADJ2, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 2), -1,
+                                      s));
+                j++;
+                kk -= 2;
+            } else {
+                v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 1 - c));
+                v.gfield = G;
+                HIP_TRY(launch_zmarch(MODE_WAVE_ADJ, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 1), -1, s));
+                j++;
+                kk -= 1;
+            }
         }
         HIP_TRY(launch_flush(G, grad, L.g, grad_scale, s));
     }

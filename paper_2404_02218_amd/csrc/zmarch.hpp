@@ -95,6 +95,9 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     constexpr int NHX = Z::NHX, NHY = Z::NHY, NHT = Z::NHT, NH = Z::NH;
     constexpr int NV = VX / 4;
     constexpr bool WAVE = MODE != MODE_HEAT;
+    // adjoint with imaging; ADJ2 also images the input level (two steps'
+    // imaging terms in one read and write of the partial g)
+    constexpr bool ADJ = MODE == MODE_WAVE_ADJ || MODE == MODE_WAVE_ADJ2, ADJ2 = MODE == MODE_WAVE_ADJ2;
     using S = Storage<T>;
     using LT = LdsT<T>;
     LT* const ldsT = reinterpret_cast<LT*>(lds);
@@ -198,8 +201,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // them at the store)
     bool dg_ok[VY];
     int64_t dg_off[VY];
-    float4 cd[VY][NV], cg[VY][NV];
-    if constexpr (MODE == MODE_WAVE_ADJ) {
+    float4 cd[VY][NV], cg[VY][NV], cd2[VY][NV];
+    if constexpr (ADJ) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
             const int y = Y0 + ty * VY + j, x0 = X0 + VX * tx;
@@ -210,6 +213,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 for (int c = 0; c < NV; c++) {
                     cd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
                     cg[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
+                    if constexpr (ADJ2)
+                        cd2[j][c] = Storage<float>::load4_nt(v.dfield2 + dg_off[j] + (int64_t)zb * sz + 4 * c);
                 }
             }
         }
@@ -259,7 +264,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 
         const bool more = z + 1 < ze;
         Raw np[VY][NV], nb[VY][NV];
-        float4 nd[VY][NV], ng[VY][NV];
+        float4 nd[VY][NV], ng[VY][NV], nd2[VY][NV];
         if (more) {
             const int64_t zn = (int64_t)(z + 1) * sz;
 #pragma unroll
@@ -276,7 +281,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     load_vec_raw<T, VX, NTH>(B + zn + own[j], nb[j]);
                 }
             }
-            if constexpr (MODE == MODE_WAVE_ADJ) {
+            if constexpr (ADJ) {
 #pragma unroll
                 for (int j = 0; j < VY; j++)
                     if (dg_ok[j]) {
@@ -284,6 +289,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                         for (int c = 0; c < NV; c++) {
                             nd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + zn + 4 * c);
                             ng[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + zn + 4 * c);
+                            if constexpr (ADJ2) nd2[j][c] = Storage<float>::load4_nt(v.dfield2 + dg_off[j] + zn + 4 * c);
                         }
                     }
             }
@@ -401,7 +407,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
                     for (int c = 0; c < NV; c++)
                         ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
-                    store_vec<T, VX>(O + off, ov, NTH && MODE != MODE_WAVE_ADJ);
+                    store_vec<T, VX>(O + off, ov, NTH && !ADJ);
                 } else {
 #pragma unroll
                     for (int i = 0; i < VX; i++)
@@ -423,7 +429,9 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                             if (x0 + i < nx) D[i] = dv[j][i];
                     }
                 }
-                if constexpr (MODE == MODE_WAVE_ADJ) {
+                // ADJ2: the input level's term first, so that the partial
+                // takes the same two roundings as after two ADJ steps
+                if constexpr (ADJ) {
                     const float* D = v.dfield + v.g.origin + off;
                     float* G = v.gfield + v.g.origin + off;
                     if (full) {
@@ -431,6 +439,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                         for (int c = 0; c < NV; c++) {
                             const float4 d = cd[j][c];
                             float4 g = cg[j][c];
+                            if constexpr (ADJ2) {
+                                const float4 d2 = cd2[j][c], uc = qi(R)[j][c];
+                                g.x = fmaf(uc.x, d2.x, g.x);
+                                g.y = fmaf(uc.y, d2.y, g.y);
+                                g.z = fmaf(uc.z, d2.z, g.z);
+                                g.w = fmaf(uc.w, d2.w, g.w);
+                            }
                             g.x = fmaf(o[j][4 * c], d.x, g.x);
                             g.y = fmaf(o[j][4 * c + 1], d.y, g.y);
                             g.z = fmaf(o[j][4 * c + 2], d.z, g.z);
@@ -438,9 +453,14 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                             Storage<float>::store4_nt(G + 4 * c, g);
                         }
                     } else {
+                        const float* D2 = v.dfield2 + v.g.origin + off;
 #pragma unroll
                         for (int i = 0; i < VX; i++)
-                            if (x0 + i < nx) G[i] = fmaf(o[j][i], D[i], G[i]);
+                            if (x0 + i < nx) {
+                                float g = G[i];
+                                if constexpr (ADJ2) g = fmaf(comp(qi(R)[j][i / 4], i % 4), D2[i], g);
+                                G[i] = fmaf(o[j][i], D[i], g);
+                            }
                     }
                 }
             }
@@ -456,9 +476,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                         cp[j][c] = widen4<T>(np[j][c]);
                         cb[j][c] = widen4<T>(nb[j][c]);
                     }
-                    if constexpr (MODE == MODE_WAVE_ADJ) {
+                    if constexpr (ADJ) {
                         cd[j][c] = nd[j][c];
                         cg[j][c] = ng[j][c];
+                        if constexpr (ADJ2) cd2[j][c] = nd2[j][c];
                     }
                 }
         }
