@@ -14,6 +14,67 @@ __device__ static inline float comp(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
+// FP16 operands through the mixed-precision FMA (v_fma_mix_f32): the named
+// half (0 low, 1 high) of a 32-bit word is read as FP16, widened exactly
+// inside the instruction, and the result rounds once in FP32.  Each form
+// equals the FP32 arithmetic on widened operands bit for bit (1.0 * m and
+// 2.0 * c are exact; a product plus -0 keeps the sign of a zero product).
+template <int HM, int HP>
+__device__ __forceinline__ float mix_add(uint32_t m, uint32_t p) {   // m + p
+    float r;
+    if constexpr (HM == 0 && HP == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(m), "v"(p));
+    else if constexpr (HM == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(m), "v"(p));
+    else if constexpr (HP == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(m), "v"(p));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(m), "v"(p));
+    return r;
+}
+template <int H>
+__device__ __forceinline__ float mix_mul(float k, uint32_t c) {   // k * c
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, %2, -%3 op_sel:[0,0,0] op_sel_hi:[0,1,0]" : "=v"(r) : "v"(k), "v"(c), "v"(0.0f));
+    else
+        asm("v_fma_mix_f32 %0, %1, %2, -%3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "=v"(r) : "v"(k), "v"(c), "v"(0.0f));
+    return r;
+}
+template <int HC, int HP>
+__device__ __forceinline__ float mix_twice_minus(uint32_t c, uint32_t p) {   // 2c - p
+    float r;
+    if constexpr (HC == 0 && HP == 0)
+        asm("v_fma_mix_f32 %0, 2.0, %1, -%2 op_sel:[0,0,0] op_sel_hi:[0,1,1]" : "=v"(r) : "v"(c), "v"(p));
+    else if constexpr (HC == 0)
+        asm("v_fma_mix_f32 %0, 2.0, %1, -%2 op_sel:[0,0,1] op_sel_hi:[0,1,1]" : "=v"(r) : "v"(c), "v"(p));
+    else if constexpr (HP == 0)
+        asm("v_fma_mix_f32 %0, 2.0, %1, -%2 op_sel:[0,1,0] op_sel_hi:[0,1,1]" : "=v"(r) : "v"(c), "v"(p));
+    else
+        asm("v_fma_mix_f32 %0, 2.0, %1, -%2 op_sel:[0,1,1] op_sel_hi:[0,1,1]" : "=v"(r) : "v"(c), "v"(p));
+    return r;
+}
+template <int H>
+__device__ __forceinline__ float mix_fma(uint32_t b, float a, float t) {   // b * a + t
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(b), "v"(a), "v"(t));
+    else
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(b), "v"(a), "v"(t));
+    return r;
+}
+template <int H>
+__device__ __forceinline__ float mix_add_f(uint32_t c, float a) {   // c + a
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(c), "v"(a));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(c), "v"(a));
+    return r;
+}
+// word w (0, 1) of a group of four 16-bit values
+__device__ __forceinline__ uint32_t word(const u2v& g, int w) { return w == 0 ? g.x : g.y; }
+
 // compile-time loop: f(integral_constant<int, I>) for I = B .. E-1
 template <int B, int E>
 struct StaticFor {
@@ -53,13 +114,18 @@ struct ZTile {
     static constexpr int NHX = 2 * TY, NHY = 2 * R * (TX / 4), NHT = NHX + NHY, NH = (NHT + NT - 1) / NT;
 };
 
-// LDS planes of BF16 fields hold the storage values as loaded (half the LDS
-// of FP32 planes, so more workgroups share a CU) and are widened per read,
-// which for BF16 is one shift or mask per value; FP32 and FP16 fields keep
-// FP32 planes (widening FP16 per read costs registers).  Values pass through
-// LDS unchanged either way.
+// LDS planes of 16-bit fields hold the storage values as loaded (half the
+// LDS of FP32 planes, so more workgroups share a CU).  BF16 values are
+// widened per read, one shift or mask per value; FP16 values stay 16-bit in
+// registers too and enter the arithmetic through the mixed-precision FMA.
+// Values pass through LDS unchanged either way.
 template <typename T>
-inline constexpr bool kLds16 = std::is_same<T, bf16>::value;
+inline constexpr bool kLds16 = std::is_same<T, bf16>::value || std::is_same<T, f16>::value;
+// FP16: the z-queue, the taps and u_prev and beta stay in the storage type
+template <typename T>
+inline constexpr bool kMix = std::is_same<T, f16>::value;
+template <typename T>
+using QGroup = typename std::conditional<kMix<T>, u2v, float4>::type;
 template <typename T>
 using LdsT = typename std::conditional<kLds16<T>, T, float>::type;
 template <typename T>
@@ -72,6 +138,9 @@ __device__ __forceinline__ void lds_put4_raw(LdsT<T>* p, typename RawGroup<T>::t
     if constexpr (kLds16<T>) *reinterpret_cast<u2v*>(p) = r;
     else *reinterpret_cast<float4*>(p) = widen4<T>(r);
 }
+// a group of the z-queue into an LDS plane
+template <typename T>
+__device__ __forceinline__ void lds_put_q(LdsT<T>* p, const QGroup<T>& g);
 // a group of 4 values that came from storage of type T (exact in T)
 template <typename T>
 __device__ __forceinline__ void lds_put4(LdsT<T>* p, float4 v) {
@@ -81,6 +150,17 @@ __device__ __forceinline__ void lds_put4(LdsT<T>* p, float4 v) {
     } else {
         *reinterpret_cast<float4*>(p) = v;
     }
+}
+template <typename T>
+__device__ __forceinline__ void lds_put_q(LdsT<T>* p, const QGroup<T>& g) {
+    if constexpr (kMix<T>) *reinterpret_cast<u2v*>(p) = g;
+    else lds_put4<T>(p, g);
+}
+// a group of an LDS plane in the z-queue's form
+template <typename T>
+__device__ __forceinline__ QGroup<T> lds_get_q(const LdsT<T>* p) {
+    if constexpr (kMix<T>) return *reinterpret_cast<const u2v*>(p);
+    else return lds_get4<T>(p);
 }
 
 // Each thread owns VX consecutive x points (VX = 4 or 8) in VY consecutive
@@ -95,6 +175,9 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     constexpr int NHX = Z::NHX, NHY = Z::NHY, NHT = Z::NHT, NH = Z::NH;
     constexpr int NV = VX / 4;
     constexpr bool WAVE = MODE != MODE_HEAT;
+    // FP16: queue, taps, u_prev and beta stay 16-bit (QG); see mix_add
+    constexpr bool MIX = kMix<T>;
+    using QG = QGroup<T>;
     // adjoint with imaging; ADJ2 also images the input level (two steps'
     // imaging terms in one read and write of the partial g)
     constexpr bool ADJ = MODE == MODE_WAVE_ADJ || MODE == MODE_WAVE_ADJ2, ADJ2 = MODE == MODE_WAVE_ADJ2;
@@ -167,11 +250,14 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 
     // own columns of planes zb-R .. zb+R; halos of planes zb .. zb+R-1 go
     // straight to their slots, the halo of plane zb+R is in flight
-    float4 q[2 * R + 1][VY][NV];
+    QG q[2 * R + 1][VY][NV];
 #pragma unroll
     for (int k = 0; k < 2 * R + 1; k++)
 #pragma unroll
-        for (int j = 0; j < VY; j++) load_vec<T, VX>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j], false);
+        for (int j = 0; j < VY; j++) {
+            if constexpr (MIX) load_vec_raw<T, VX, false>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j]);
+            else load_vec<T, VX>(U + (int64_t)(zb - R + k) * sz + own[j], q[k][j], false);
+        }
     for (int p = zb; p < min(zb + R, ze); p++) {
         LT* L = ldsT + ((p - zb) % NSLOT) * PLANE;
 #pragma unroll
@@ -186,12 +272,17 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         for (int m = 0; m < NH; m++)
             if (hon[m]) hal[m] = load4_raw<T, false>(U + (int64_t)(zb + R) * sz + hoff[m]);
     }
-    float4 cp[VY][NV], cb[VY][NV];
+    QG cp[VY][NV], cb[VY][NV];
     if constexpr (WAVE) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
-            load_vec<T, VX>(P + (int64_t)zb * sz + own[j], cp[j], NTH);
-            load_vec<T, VX>(B + (int64_t)zb * sz + own[j], cb[j], NTH);
+            if constexpr (MIX) {
+                load_vec_raw<T, VX, NTH>(P + (int64_t)zb * sz + own[j], cp[j]);
+                load_vec_raw<T, VX, NTH>(B + (int64_t)zb * sz + own[j], cb[j]);
+            } else {
+                load_vec<T, VX>(P + (int64_t)zb * sz + own[j], cp[j], NTH);
+                load_vec<T, VX>(B + (int64_t)zb * sz + own[j], cb[j], NTH);
+            }
         }
     }
 
@@ -248,13 +339,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     Raw nq[VY][NV];   // the next leading plane, in flight during the compute
     auto step = [&](auto off_c) {
         constexpr int OFF = decltype(off_c)::value;
-        auto qi = [&](int k) -> float4(&)[VY][NV] { return q[(k + OFF) % Q]; };
+        auto qi = [&](int k) -> QG(&)[VY][NV] { return q[(k + OFF) % Q]; };
         LT* L = ldsT + slot * PLANE;
 #pragma unroll
         for (int j = 0; j < VY; j++)
 #pragma unroll
             for (int c = 0; c < NV; c++)
-                lds_put4<T>(&L[(R + ty * VY + j) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
+                lds_put_q<T>(&L[(R + ty * VY + j) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
         if (z + R < ze) {
             LT* H = ldsT + hslot * PLANE;
 #pragma unroll
@@ -303,7 +394,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         // y tap rows row0 - R .. row0 + VY - 1 + R of this thread's columns:
         // its own rows from the z-queue, the 2R others from LDS, once each
         const int row0 = R + ty * VY;
-        float4 yr[VY + 2 * R][NV];
+        QG yr[VY + 2 * R][NV];
 #pragma unroll
         for (int q2 = 0; q2 < VY + 2 * R; q2++)
 #pragma unroll
@@ -311,12 +402,53 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 if (q2 >= R && q2 < R + VY)
                     yr[q2][c] = qi(R)[q2 - R][c];
                 else
-                    yr[q2][c] = lds_get4<T>(L + (row0 - R + q2) * LDX + 4 + VX * tx + 4 * c);
+                    yr[q2][c] = lds_get_q<T>(L + (row0 - R + q2) * LDX + 4 + VX * tx + 4 * c);
             }
 #pragma unroll
         for (int j = 0; j < VY; j++) {
             const int row = row0 + j;
             const LT* Lr = L + row * LDX + VX * tx;
+            if constexpr (MIX) {
+                // x taps as 16-bit halves of words: 4 left of the thread's
+                // points (words 0, 1), its own VX, 4 right; the same
+                // canonical order as below, each pair sum read straight
+                // from the halves
+                uint32_t xw[VX / 2 + 4];
+                {
+                    const u2v xl = *reinterpret_cast<const u2v*>(Lr);
+                    const u2v xr = *reinterpret_cast<const u2v*>(Lr + 4 + VX);
+                    xw[0] = xl.x;
+                    xw[1] = xl.y;
+#pragma unroll
+                    for (int c = 0; c < NV; c++) {
+                        xw[2 + 2 * c] = qi(R)[j][c].x;
+                        xw[3 + 2 * c] = qi(R)[j][c].y;
+                    }
+                    xw[VX / 2 + 2] = xr.x;
+                    xw[VX / 2 + 3] = xr.y;
+                }
+                StaticFor<0, VX>::run([&](auto ic) {
+                    constexpr int i = decltype(ic)::value, c = i / 4, wd = (i % 4) / 2, h = i % 2;
+                    float acc = mix_mul<h>(w.cd0, word(qi(R)[j][c], wd));
+                    StaticFor<1, R + 1>::run([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        acc = fmaf(w.c[k], mix_add<h, h>(word(qi(R - k)[j][c], wd), word(qi(R + k)[j][c], wd)), acc);
+                    });
+                    StaticFor<1, R + 1>::run([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        acc = fmaf(w.c[k], mix_add<h, h>(word(yr[R + j - k][c], wd), word(yr[R + j + k][c], wd)), acc);
+                    });
+                    StaticFor<1, R + 1>::run([&](auto kc) {
+                        constexpr int k = decltype(kc)::value, hm = 4 + i - k, hp = 4 + i + k;
+                        acc = fmaf(w.c[k], mix_add<hm % 2, hp % 2>(xw[hm / 2], xw[hp / 2]), acc);
+                    });
+                    if constexpr (WAVE)
+                        o[j][i] = mix_fma<h>(word(cb[j][c], wd), acc,
+                                             mix_twice_minus<h, h>(word(qi(R)[j][c], wd), word(cp[j][c], wd)));
+                    else
+                        o[j][i] = mix_add_f<h>(word(qi(R)[j][c], wd), acc);
+                });
+            } else {
             // x taps: 4 left of the thread's points, its own VX, 4 right
             float xv[VX + 8];
             {
@@ -333,7 +465,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 xv[VX + 6] = xr.z;
                 xv[VX + 7] = xr.w;
             }
-            float4 ym[R][NV], yp[R][NV];
+            QG ym[R][NV], yp[R][NV];
 #pragma unroll
             for (int k = 1; k <= R; k++)
 #pragma unroll
@@ -374,6 +506,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 } else {
                     o[j][i] = time_update<MODE>(acc, ctr, 0.f, 0.f);
                 }
+            }
             }
         }
         if constexpr (WAVE) {
@@ -471,10 +604,18 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             for (int j = 0; j < VY; j++)
 #pragma unroll
                 for (int c = 0; c < NV; c++) {
-                    q[OFF][j][c] = widen4<T>(nq[j][c]);
-                    if constexpr (WAVE) {
-                        cp[j][c] = widen4<T>(np[j][c]);
-                        cb[j][c] = widen4<T>(nb[j][c]);
+                    if constexpr (MIX) {
+                        q[OFF][j][c] = nq[j][c];
+                        if constexpr (WAVE) {
+                            cp[j][c] = np[j][c];
+                            cb[j][c] = nb[j][c];
+                        }
+                    } else {
+                        q[OFF][j][c] = widen4<T>(nq[j][c]);
+                        if constexpr (WAVE) {
+                            cp[j][c] = widen4<T>(np[j][c]);
+                            cb[j][c] = widen4<T>(nb[j][c]);
+                        }
                     }
                     if constexpr (ADJ) {
                         cd[j][c] = nd[j][c];

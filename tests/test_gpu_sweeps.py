@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_2404_02218_amd as S
 import workloads as W
-from _helpers import gpu_heat, gpu_wave, oracle_wave, rel_err, torch_f64, wave_inputs
+from _helpers import DT_NAMES, gpu_heat, gpu_wave, oracle_wave, rel_err, torch_f64, wave_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +47,22 @@ def test_heat3d_so4_all_variants_bitwise_and_parity(device, shape):
     c = [0.05 * x for x in oracle.fd_weights_float(4)]
     ref = W.interior_of(oracle.heat_run(W.embed(u0, 2), 2, 2, c, 12), 2)
     assert rel_err(base, ref) <= TOL_F32
+    for v in range(1, plan.variant_count()):
+        got = gpu_heat(plan, u0, 12, variant=v)
+        assert np.array_equal(got, base), plan.variant_name(v)
+
+
+@pytest.mark.parametrize("dtype", [S.BF16, S.F16])
+@pytest.mark.parametrize("radius", [2, 4])
+def test_heat3d_16bit_all_variants_bitwise(device, dtype, radius):
+    # every z-marching variant of a 16-bit heat plan equals the
+    # one-point-per-thread kernel bit for bit (ragged tiles in x and y)
+    shape = (37, 45, 83)
+    rng = np.random.default_rng(23)
+    u0 = W.round_to_storage(rng.random(shape) + W.gaussian_bump(shape, 6.0), DT_NAMES[dtype])
+    plan = S.Plan(S.HEAT, shape, radius, S.heat_weights(2 * radius, 0.05), halo=radius, dtype=dtype)
+    base = gpu_heat(plan, u0, 12, variant=0)
+    assert np.all(np.isfinite(base)) and np.abs(base).max() > 0
     for v in range(1, plan.variant_count()):
         got = gpu_heat(plan, u0, 12, variant=v)
         assert np.array_equal(got, base), plan.variant_name(v)
@@ -106,13 +122,18 @@ def test_wave3d_so8_parity_with_source_and_receivers(device, shape):
     assert rel_err(tr, rtr) <= TOL_F32
 
 
-def test_wave3d_all_variants_bitwise(device):
+@pytest.mark.parametrize("dtype", [S.F32, S.BF16, S.F16])
+def test_wave3d_all_variants_bitwise(device, dtype):
+    # variant 0 is the one-point-per-thread kernel, which widens every operand
+    # and computes in FP32; the z-marching variants (FP16: operands read as
+    # FP16 by the mixed-precision FMA) and the temporally blocked ones must
+    # give the same bits, with ragged tile edges and sources on the faces
     shape = (45, 38, 97)
-    u0, um1, beta = wave_inputs(shape, seed=41)
+    u0, um1, beta = wave_inputs(shape, seed=41, dtype=dtype)
     src = np.array([[20, 30, 90], [44, 0, 0]])
     rec = np.array([[20, 30, 90], [3, 3, 3]])
     amp = np.random.default_rng(42).standard_normal((9, 2))
-    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4)
+    plan = S.Plan(S.WAVE2, shape, 4, S.second_derivative_weights(8), halo=4, dtype=dtype)
     base = gpu_wave(plan, u0, um1, beta, 9, src=src, amp=amp, rec=rec, variant=0)
     for v in range(1, plan.variant_count()):
         got = gpu_wave(plan, u0, um1, beta, 9, src=src, amp=amp, rec=rec, variant=v)
