@@ -127,10 +127,10 @@ std::shared_ptr<RtcProgram> program_compile(const std::string& src, int threads,
 hipError_t launch_program_rtc(RtcProgram& rp, const ProgView& v, hipStream_t s);
 
 // Tile shapes of the z-marching kernel: BX threads along x with VX points
-// each, BY thread rows, each thread owning VY rows (strided by BY); nt: stream
+// each, BY thread rows, each thread owning VY consecutive rows; nt: stream
 // the once-read previous level and beta with non-temporal loads and the
 // output with non-temporal stores.  VX = 8 gives 16-byte accesses for 16-bit
-// storage.
+// storage (the fastest FP16 sweeps use it).
 struct TileCfg {
     int bx, by, vy, vx;
     bool nt;
@@ -138,7 +138,7 @@ struct TileCfg {
 inline constexpr TileCfg kTileCfgs[] = {
     {16, 16, 2, 4, false},  // 64 x 32 tile, 256 threads
     {16, 16, 1, 4, true},   // 64 x 16 tile, 256 threads, streaming hints
-    {32, 8, 2, 4, false},   // 128 x 16 tile, 256 threads
+    {8, 32, 1, 8, true},    // 64 x 32 tile, 256 threads, 8 points per lane, streaming hints
     {16, 16, 1, 4, false},  // 64 x 16 tile, 256 threads
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);

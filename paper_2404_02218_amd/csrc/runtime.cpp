@@ -2536,7 +2536,7 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
         const Variant v = variant_of(variant);
         name = "zmarch_" + std::to_string(tile_tx(v.cfg)) + "x" + std::to_string(tile_ty(v.cfg)) + "_t" +
                std::to_string(tile_threads(v.cfg)) + "_zc" + std::to_string(v.zc) +
-               (kTileCfgs[v.cfg].nt ? "_nt" : "");
+               (kTileCfgs[v.cfg].vx == 8 ? "_p8" : "") + (kTileCfgs[v.cfg].nt ? "_nt" : "");
     }
     std::snprintf(buf, len, "%s", name.c_str());
     return STENCIL_OK;
