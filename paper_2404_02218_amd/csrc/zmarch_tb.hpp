@@ -133,15 +133,25 @@ __device__ __forceinline__ void tb2_star(const Coefs& w, ZT&& zt, const float* L
     }
 }
 
+// Point lists and amplitudes are invariant during a launch: reading them
+// through the constant address space makes them scalar loads, which the
+// vector memory counter does not track.  (As vector loads whose results only
+// some lanes use, they made the compiler wait for every outstanding load and
+// store of the wave before stage 2.)
+template <typename U>
+__device__ __forceinline__ U tb2_ldc(const U* p) {
+    return *(const __attribute__((address_space(4))) U*)p;
+}
+
 // first source of a tile's z-sorted list at or after plane z0
 __device__ static inline void tb2_src_first(const SrcList& s, int tile, int z0, int& next, int& end, int& znext) {
     next = end = 0;
     znext = INT_MAX;
     if (s.n > 0) {
-        next = s.tile_begin[tile];
-        end = s.tile_begin[tile + 1];
-        while (next < end && s.zyx4[4 * next] < z0) next++;
-        znext = next < end ? s.zyx4[4 * next] : INT_MAX;
+        next = tb2_ldc(s.tile_begin + tile);
+        end = tb2_ldc(s.tile_begin + tile + 1);
+        while (next < end && tb2_ldc(s.zyx4 + 4 * next) < z0) next++;
+        znext = next < end ? tb2_ldc(s.zyx4 + 4 * next) : INT_MAX;
     }
 }
 
@@ -362,6 +372,7 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         tb2_src_first(v.src_t, tile, zb, t_next, t_end, t_z);
     }
 
+    float o2p[4] = {0.f, 0.f, 0.f, 0.f};   // u^{n+2} of the previous plane, stored with the next plane
     int it = 0;   // plane counter: u^n LDS slot it & 1
     int s2 = 0;   // LDS slot of u^{n+1} plane z1
     int z1 = z1b;
@@ -383,15 +394,26 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         }
 
         const bool more = z1 + 1 < z1e;
-        // the next plane's loads, in flight during the compute
+        // the next plane's loads, in flight during the compute (past the
+        // chunk their planes are clamped and the values go unused)
         Raw nq, np, nb, nm;
-        if (more) {
-            nq = ldr(rU, z1 + 1 + R, ag);
-            if constexpr (WAVE) {
-                np = ldr(rP, z1 + 1, ag);
-                nb = ldr(rB, z1 + 1, ag);
+        nq = ldr(rU, z1 + 1 + R, ag);
+        if constexpr (WAVE) {
+            np = ldr(rP, z1 + 1, ag);
+            nb = ldr(rB, z1 + 1, ag);
+        }
+        if (!tile_role) nm = ldr(rU, z1 + 1 + R, am);
+        // the previous plane's stores, issued after these loads so that the
+        // wait for the loads at the end of the plane does not also wait for
+        // them: u^{n+1} at z1 - 1 (still in the column ring) and u^{n+2} at
+        // z1 - 1 - R
+        if (tile_role && store_ok) {
+            if (WAVE && z1 - 1 >= zb && z1 - 1 < ze) {
+                const float4 p1 = zb2(2 * R - 1);
+                const float o[4] = {p1.x, p1.y, p1.z, p1.w};
+                tb2_store<T>(rO1, ag, soff(z1 - 1), full_tile, x0, nx, o);
             }
-            if (!tile_role) nm = ldr(rU, z1 + 1 + R, am);
+            if (z1 - 1 - R >= zb) tb2_store<T>(rO2, ag, soff(z1 - 1 - R), full_tile, x0, nx, o2p);
         }
         __syncthreads();
 
@@ -404,11 +426,12 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
             while (WAVE && e_z == z1) {
                 const int* e = v.src_e.zyx4 + 4 * e_next;
                 e_next++;
-                e_z = e_next < e_end ? v.src_e.zyx4[4 * e_next] : INT_MAX;
-                const double amt = v.src_e.amp[(int64_t)arow * v.src_e.n + e[3]];
+                e_z = e_next < e_end ? tb2_ldc(v.src_e.zyx4 + 4 * e_next) : INT_MAX;
+                const int ey = tb2_ldc(e + 1), ex = tb2_ldc(e + 2);
+                const double amt = tb2_ldc(v.src_e.amp + (int64_t)arow * v.src_e.n + tb2_ldc(e + 3));
 #pragma unroll
                 for (int i = 0; i < 4; i++)
-                    if (e[1] == y0 && e[2] == x0 + i) o[i] = inject<T>(o[i], amt);
+                    if (ey == y0 && ex == x0 + i) o[i] = inject<T>(o[i], amt);
             }
             r1.x = zin && in[0] ? through<T>(o[0]) : 0.f;
             r1.y = zin && in[1] ? through<T>(o[1]) : 0.f;
@@ -420,10 +443,6 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         // ---- stage 2 (tile role): u^{n+2} at plane z = z1 - R
         if (tile_role) {
             qx[(2 * R + OFF2) % Q] = r1;
-            if (WAVE && z1 >= zb && z1 < ze && store_ok) {
-                const float o[4] = {r1.x, r1.y, r1.z, r1.w};
-                tb2_store<T>(rO1, ag, soff(z1), full_tile, x0, nx, o);
-            }
             const int z = z1 - R;
             if (z >= zb) {
                 const int sz2 = s2 + 1 == NS2 ? 0 : s2 + 1;   // slot of plane z1 - R
@@ -436,13 +455,15 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
                 while (WAVE && t_z == z) {
                     const int* e = v.src_t.zyx4 + 4 * t_next;
                     t_next++;
-                    t_z = t_next < t_end ? v.src_t.zyx4[4 * t_next] : INT_MAX;
-                    const double amt = v.src_t.amp[(int64_t)(arow + 1) * v.src_t.n + e[3]];
+                    t_z = t_next < t_end ? tb2_ldc(v.src_t.zyx4 + 4 * t_next) : INT_MAX;
+                    const int ey = tb2_ldc(e + 1), ex = tb2_ldc(e + 2);
+                    const double amt = tb2_ldc(v.src_t.amp + (int64_t)(arow + 1) * v.src_t.n + tb2_ldc(e + 3));
 #pragma unroll
                     for (int i = 0; i < 4; i++)
-                        if (e[1] == y0 && e[2] == x0 + i) o2[i] = inject<T>(o2[i], amt);
+                        if (ey == y0 && ex == x0 + i) o2[i] = inject<T>(o2[i], amt);
                 }
-                if (store_ok) tb2_store<T>(rO2, ag, soff(z), full_tile, x0, nx, o2);
+#pragma unroll
+                for (int i = 0; i < 4; i++) o2p[i] = o2[i];
             }
         }
 
@@ -462,6 +483,8 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
     StaticFor<0, Q - 1>::run([&](auto c) __attribute__((always_inline)) {
         if (z1 < z1e) step(c);
     });
+    // the last plane's u^{n+2} (its u^{n+1} lies past the chunk)
+    if (tile_role && store_ok && z1 - 1 - R >= zb) tb2_store<T>(rO2, ag, soff(z1 - 1 - R), full_tile, x0, nx, o2p);
 }
 
 template <int MODE, int R, typename T>
