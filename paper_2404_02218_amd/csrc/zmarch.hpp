@@ -14,6 +14,15 @@ __device__ static inline float comp(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
+// Point lists and amplitudes are invariant during a launch: reading them
+// through the constant address space makes them scalar loads, which the
+// vector memory counter does not track (as vector loads used by some lanes
+// only, they made the compiler wait for every outstanding load and store).
+template <typename U>
+__device__ __forceinline__ U ld_inv(const U* p) {
+    return *(const __attribute__((address_space(4))) U*)p;
+}
+
 // FP16 operands through the mixed-precision FMA (v_fma_mix_f32): the named
 // half (0 low, 1 high) of a 32-bit word is read as FP16, widened exactly
 // inside the instruction, and the result rounds once in FP32.  Each form
@@ -181,6 +190,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // adjoint with imaging; ADJ2 also images the input level (two steps'
     // imaging terms in one read and write of the partial g)
     constexpr bool ADJ = MODE == MODE_WAVE_ADJ || MODE == MODE_WAVE_ADJ2, ADJ2 = MODE == MODE_WAVE_ADJ2;
+    // forward modes: a plane's output goes out after the next plane's loads,
+    // which are issued on every plane, so the waits for those loads count the
+    // same operations on every path and never wait for the stores
+    constexpr bool DEFER = !ADJ && MODE != MODE_WAVE_D;
     using S = Storage<T>;
     using LT = LdsT<T>;
     LT* const ldsT = reinterpret_cast<LT*>(lds);
@@ -320,10 +333,10 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     if constexpr (WAVE) {
         if (v.src.n > 0) {
             const int tile = tile_y * v.ntx + tile_x;
-            snext = v.src.tile_begin[tile];
-            se = v.src.tile_begin[tile + 1];
-            while (snext < se && v.src.zyx4[4 * snext] < zb) snext++;
-            szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
+            snext = ld_inv(v.src.tile_begin + tile);
+            se = ld_inv(v.src.tile_begin + tile + 1);
+            while (snext < se && ld_inv(v.src.zyx4 + 4 * snext) < zb) snext++;
+            szn = snext < se ? ld_inv(v.src.zyx4 + 4 * snext) : INT_MAX;
         }
     }
 
@@ -337,6 +350,29 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // 2R+1 times so that every offset is a constant.
     constexpr int Q = 2 * R + 1;
     Raw nq[VY][NV];   // the next leading plane, in flight during the compute
+    float o[VY][VX];  // the plane's output (DEFER: stored during the next plane)
+    // store o as plane zs of the output (the rows and columns in the interior)
+    auto store_out = [&](int zs) {
+#pragma unroll
+        for (int j = 0; j < VY; j++) {
+            const int y = Y0 + ty * VY + j;
+            const int x0 = X0 + VX * tx;
+            if (y < ny && x0 < nx) {
+                const int64_t off = (int64_t)zs * sz + (int64_t)y * sy + x0;
+                if (x0 + VX - 1 < nx) {
+                    float4 ov[NV];
+#pragma unroll
+                    for (int c = 0; c < NV; c++)
+                        ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
+                    store_vec<T, VX>(O + off, ov, NTH && !ADJ);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < VX; i++)
+                        if (x0 + i < nx) S::store(O + off + i, o[j][i]);
+                }
+            }
+        }
+    };
     auto step = [&](auto off_c) {
         constexpr int OFF = decltype(off_c)::value;
         auto qi = [&](int k) -> QG(&)[VY][NV] { return q[(k + OFF) % Q]; };
@@ -356,11 +392,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         const bool more = z + 1 < ze;
         Raw np[VY][NV], nb[VY][NV];
         float4 nd[VY][NV], ng[VY][NV], nd2[VY][NV];
-        if (more) {
-            const int64_t zn = (int64_t)(z + 1) * sz;
+        if (DEFER || more) {
+            // DEFER: past the chunk the loads re-read the current plane's
+            // rows (in the field; the values go unused)
+            const int64_t zn = (int64_t)(more ? z + 1 : z) * sz;
 #pragma unroll
             for (int j = 0; j < VY; j++) load_vec_raw<T, VX, false>(U + zn + (int64_t)R * sz + own[j], nq[j]);
-            if (z + R + 1 < ze) {
+            if (DEFER || z + R + 1 < ze) {
 #pragma unroll
                 for (int m = 0; m < NH; m++)
                     if (hon[m]) hal[m] = load4_raw<T, false>(U + zn + (int64_t)R * sz + hoff[m]);
@@ -385,11 +423,13 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                     }
             }
         }
+        if constexpr (DEFER) {
+            if (z > zb) store_out(z - 1);
+        }
         __syncthreads();
 
         float dgz = 0.f;
         if constexpr (MODE == MODE_WAVE_DAMP) dgz = v.damp[z];
-        float o[VY][VX];
         float dv[VY][VX];
         // y tap rows row0 - R .. row0 + VY - 1 + R of this thread's columns:
         // its own rows from the z-queue, the 2R others from LDS, once each
@@ -513,10 +553,11 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             while (szn == z) {
                 const int* e = v.src.zyx4 + 4 * snext;
                 snext++;
-                szn = snext < se ? v.src.zyx4[4 * snext] : INT_MAX;
-                const int dy = e[1] - Y0, dx = e[2] - X0;
-                const int idx = e[3];
-                const double amt = v.src.amp[(int64_t)arow * v.src.n + idx] * (v.src.scale ? v.src.scale[idx] : 1.0);
+                szn = snext < se ? ld_inv(v.src.zyx4 + 4 * snext) : INT_MAX;
+                const int dy = ld_inv(e + 1) - Y0, dx = ld_inv(e + 2) - X0;
+                const int idx = ld_inv(e + 3);
+                const double amt =
+                    ld_inv(v.src.amp + (int64_t)arow * v.src.n + idx) * (v.src.scale ? ld_inv(v.src.scale + idx) : 1.0);
 #pragma unroll
                 for (int j = 0; j < VY; j++)
 #pragma unroll
@@ -535,16 +576,18 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             if (y < ny && x0 < nx) {
                 const int64_t off = (int64_t)z * sz + (int64_t)y * sy + x0;
                 const bool full = x0 + VX - 1 < nx;
-                if (full) {
-                    float4 ov[NV];
+                if constexpr (!DEFER) {
+                    if (full) {
+                        float4 ov[NV];
 #pragma unroll
-                    for (int c = 0; c < NV; c++)
-                        ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
-                    store_vec<T, VX>(O + off, ov, NTH && !ADJ);
-                } else {
+                        for (int c = 0; c < NV; c++)
+                            ov[c] = make_float4(o[j][4 * c], o[j][4 * c + 1], o[j][4 * c + 2], o[j][4 * c + 3]);
+                        store_vec<T, VX>(O + off, ov, NTH && !ADJ);
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < VX; i++)
-                        if (x0 + i < nx) S::store(O + off + i, o[j][i]);
+                        for (int i = 0; i < VX; i++)
+                            if (x0 + i < nx) S::store(O + off + i, o[j][i]);
+                    }
                 }
                 // D (written by the recompute, read once by the adjoint many
                 // steps later) and the imaging partial G (read and written once
@@ -632,6 +675,9 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     StaticFor<0, Q - 1>::run([&](auto c) {
         if (z < ze) step(c);
     });
+    if constexpr (DEFER) {
+        if (z > zb) store_out(z - 1);
+    }
 }
 
 template <int MODE, int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
