@@ -236,6 +236,10 @@ template <int MODE, int R_, typename T>
 __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb, int arow, int trow_u, int trow_p,
                                          float* __restrict__ lds) {
     constexpr bool WAVE = MODE != MODE_HEAT, DAMP = MODE == MODE_WAVE_DAMP;
+    // wave modes: a plane's stores go out after the next plane's loads (see
+    // below); the heat form, with one load per plane and 6 waves per SIMD,
+    // runs faster storing each plane as it is computed
+    constexpr bool DEFER = WAVE;
     using Z = TB2<R_, WAVE>;
     using S = Storage<T>;
     constexpr int R = Z::R, Q = Z::Q, TX = Z::TX, TY = Z::TY, NT = Z::NT;
@@ -397,17 +401,19 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         // the next plane's loads, in flight during the compute (past the
         // chunk their planes are clamped and the values go unused)
         Raw nq, np, nb, nm;
-        nq = ldr(rU, z1 + 1 + R, ag);
-        if constexpr (WAVE) {
-            np = ldr(rP, z1 + 1, ag);
-            nb = ldr(rB, z1 + 1, ag);
+        if (DEFER || more) {
+            nq = ldr(rU, z1 + 1 + R, ag);
+            if constexpr (WAVE) {
+                np = ldr(rP, z1 + 1, ag);
+                nb = ldr(rB, z1 + 1, ag);
+            }
+            if (!tile_role) nm = ldr(rU, z1 + 1 + R, am);
         }
-        if (!tile_role) nm = ldr(rU, z1 + 1 + R, am);
         // the previous plane's stores, issued after these loads so that the
         // wait for the loads at the end of the plane does not also wait for
         // them: u^{n+1} at z1 - 1 (still in the column ring) and u^{n+2} at
         // z1 - 1 - R
-        if (tile_role && store_ok) {
+        if (DEFER && tile_role && store_ok) {
             if (WAVE && z1 - 1 >= zb && z1 - 1 < ze) {
                 const float4 p1 = zb2(2 * R - 1);
                 const float o[4] = {p1.x, p1.y, p1.z, p1.w};
@@ -462,8 +468,12 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
                     for (int i = 0; i < 4; i++)
                         if (ey == y0 && ex == x0 + i) o2[i] = inject<T>(o2[i], amt);
                 }
+                if constexpr (DEFER) {
 #pragma unroll
-                for (int i = 0; i < 4; i++) o2p[i] = o2[i];
+                    for (int i = 0; i < 4; i++) o2p[i] = o2[i];
+                } else if (store_ok) {
+                    tb2_store<T>(rO2, ag, soff(z), full_tile, x0, nx, o2);
+                }
             }
         }
 
@@ -484,7 +494,8 @@ __device__ __forceinline__ void tb2_tile(const TBView& v, const Coefs& w, int lb
         if (z1 < z1e) step(c);
     });
     // the last plane's u^{n+2} (its u^{n+1} lies past the chunk)
-    if (tile_role && store_ok && z1 - 1 - R >= zb) tb2_store<T>(rO2, ag, soff(z1 - 1 - R), full_tile, x0, nx, o2p);
+    if (DEFER && tile_role && store_ok && z1 - 1 - R >= zb)
+        tb2_store<T>(rO2, ag, soff(z1 - 1 - R), full_tile, x0, nx, o2p);
 }
 
 template <int MODE, int R, typename T>
