@@ -1909,6 +1909,9 @@ static std::vector<std::vector<int>> branch_lists(const stencil_plan_s* p) {
         load[b] += work(i);
         lists[b].push_back(i);
     }
+    // every other branch runs its shots smallest first, so that large and
+    // small shots share the GPU through the run
+    for (int b = 1; b < kBranches; b += 2) std::reverse(lists[b].begin(), lists[b].end());
     return lists;
 }
 
