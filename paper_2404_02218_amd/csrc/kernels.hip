@@ -21,6 +21,7 @@
 //            copies (halo pack, unpack, periodic self-exchange), zero fill,
 //            beta from squared slowness, FP64 gradient flush.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -183,6 +184,24 @@ __global__ __launch_bounds__(256) void k_boxcopy(T* __restrict__ field, int64_t 
 __global__ void k_zero(uint32_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+// one block per row of the allocation (plane pz, row r); block `rows` clears
+// the tail past the last row
+__global__ void k_zero_frame(uint32_t* p, Grid3 g, int halo, int rows, int tail) {
+    const int q = blockIdx.x;
+    const int rowlen = (int)g.rowlen;
+    uint32_t* row = p + (int64_t)q * rowlen;
+    if (q == rows) {
+        for (int c = threadIdx.x; c < tail; c += blockDim.x) row[c] = 0u;
+        return;
+    }
+    const int ey = g.n[1] + 2 * halo;
+    const int pz = q / ey, r = q - pz * ey;
+    const bool frame = pz < halo || pz >= halo + g.n[0] || r < halo || r >= halo + g.n[1];
+    const int xb = (int)g.xlead, xe = xb + g.n[2];
+    for (int c = threadIdx.x; c < rowlen; c += blockDim.x)
+        if (frame || c < xb || c >= xe) row[c] = 0u;
 }
 
 template <typename T>
@@ -418,6 +437,16 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
     const int64_t n = bytes / 4;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256)), dim3(256), 0, s, (uint32_t*)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_frame(void* p, const Grid3& g, int halo, int64_t elems, hipStream_t s) {
+    const int64_t rows = (int64_t)(g.n[0] + 2 * halo) * (g.n[1] + 2 * halo);
+    if (g.nd != 3 || g.s[1] != g.rowlen || g.s[0] != (g.n[1] + 2 * halo) * g.rowlen || rows * g.rowlen > elems ||
+        elems - rows * g.rowlen > 1024 || rows >= INT_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_frame, dim3((unsigned)rows + 1), dim3(128), 0, s, (uint32_t*)p, g, halo, (int)rows,
+                       (int)(elems - rows * g.rowlen));
     return hipGetLastError();
 }
 

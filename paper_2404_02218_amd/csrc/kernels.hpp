@@ -222,6 +222,10 @@ hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecL
 hipError_t launch_boxcopy(int dtype, int dir, void* field, const Grid3& g, int64_t offset, const CopyList& L,
                           void* buf, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+// zero every 32-bit element of a 3D FP32 field allocation of `elems`
+// elements except its interior (halo planes, rows and columns, the row
+// padding and the tail), so that a sweep can write into it as its output
+hipError_t launch_zero_frame(void* p, const Grid3& g, int halo, int64_t elems, hipStream_t s);
 hipError_t launch_beta(int dtype, const double* m, void* beta, const Grid3& g, double scale, hipStream_t s);
 hipError_t launch_flush(float* g32, double* grad, const Grid3& g, double scale, hipStream_t s);
 

@@ -2149,6 +2149,18 @@ static Variant adjoint_variant(stencil_plan p) {
 }
 
 // Forward run storing (u^c, u^{c-1}) every k steps (arguments validated)
+// The buffers of one segment's levels: u^{t0} and u^{t0-1} in (cur, prv),
+// then u^{t0+i} alternating between two other buffers, odd i in y and even
+// i in x.  Step j reads levels j and j - 1 and writes level j + 1 (from the
+// third step on, in place over level j - 1, as the plain run does).
+struct SegLevels {
+    void* cur;
+    void* prv;
+    void* x;
+    void* y;
+    void* at(int64_t i) const { return i < 0 ? prv : i == 0 ? cur : (i & 1) ? y : x; }
+};
+
 static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t nsteps, int64_t k,
                                         const stencil_source* src, const stencil_receivers* rec, void* ws,
                                         const AdjLayout& A, hipStream_t s) {
@@ -2160,24 +2172,39 @@ static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t n
     void* b = fields[1];
     const SrcList sl = src_list(p->src, src ? src->amp : nullptr, nullptr);
     const RecList rl = rec_list(p->rec, rec ? rec->trace : nullptr);
-    for (int64_t t = 0; t < nsteps; t++) {
-        const int parity = (int)(t & 1);
-        if (t % k == 0) {
-            const int64_t c = t / k;
-            HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 2 * c), parity ? b : a, L.bytes, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 2 * c + 1), parity ? a : b, L.bytes, hipMemcpyDeviceToDevice, s));
+    // Checkpoint c is the slot pair (u^{ck}, u^{ck-1}).  Pair 0 is a copy of
+    // the initial state; segment c then sweeps from pair c into pair c + 1,
+    // so the sweeps write the later checkpoints themselves, and the last
+    // segment sweeps into the caller's fields (u^N into a for even N, into b
+    // for odd N, as the plain run leaves them).
+    HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0), a, L.bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 1), b, L.bytes, hipMemcpyDeviceToDevice, s));
+    for (int64_t c = 2; c < 2 * A.nseg; c++)
+        HIP_TRY(launch_zero_frame(slot(ws, A, A.ckpt0 + c), L.g, L.halo, L.elems, s));
+    for (int64_t c = 0; c < A.nseg; c++) {
+        const int64_t t0 = c * k, len = std::min(t0 + k, nsteps) - t0;
+        const bool last = c + 1 == A.nseg;
+        void* const cur = slot(ws, A, A.ckpt0 + 2 * c);
+        void* const prv = slot(ws, A, A.ckpt0 + 2 * c + 1);
+        void* const tu = last ? ((nsteps & 1) ? b : a) : slot(ws, A, A.ckpt0 + 2 * c + 2);
+        void* const tp = last ? ((nsteps & 1) ? a : b) : slot(ws, A, A.ckpt0 + 2 * c + 3);
+        const SegLevels lv{cur, prv, (len & 1) ? tp : tu, (len & 1) ? tu : tp};
+        for (int64_t j = 0; j < len; j++) {
+            const int64_t t = t0 + j;
+            ZView v{};
+            v.u = lv.at(j);
+            v.prev = lv.at(j - 1);
+            v.out = lv.at(j + 1);
+            v.beta = fields[2];
+            v.g = L.g;
+            set_tiling(v, L, var);
+            v.src = sl;
+            v.rec = rl;
+            HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t,
+                                  (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1, s));
         }
-        ZView v{};
-        v.u = a;
-        v.prev = b;
-        v.out = b;
-        v.beta = fields[2];
-        v.g = L.g;
-        set_tiling(v, L, var);
-        v.src = sl;
-        v.rec = rl;
-        HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, parity, (int)t,
-                              (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1, s));
+        // one-step segment: u^{t0} is still only in pair c
+        if (len == 1) HIP_TRY(hipMemcpyAsync(tp, cur, L.bytes, hipMemcpyDeviceToDevice, s));
     }
     if (rl.n > 0) HIP_TRY(launch_record(p->dtype, (nsteps & 1) ? b : a, L.g, rl, (int)(nsteps - 1), s));
     if (nsteps & 1) std::swap(fields[0], fields[1]);
@@ -2205,22 +2232,25 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
     HIP_TRY(launch_zero(L0, L.bytes, s));
     HIP_TRY(launch_zero(L1, L.bytes, s));
     HIP_TRY(launch_zero(G, L.bytes, s));
+    HIP_TRY(launch_zero_frame(F0, L.g, L.halo, L.elems, s));
+    HIP_TRY(launch_zero_frame(F1, L.g, L.halo, L.elems, s));
     int64_t j = 0;  // adjoint steps taken (parity of the lambda buffers)
     for (int64_t sg = A.nseg - 1; sg >= 0; sg--) {
         const int64_t c = sg * k, ce = std::min(c + k, nsteps);
-        HIP_TRY(hipMemcpyAsync(F0, slot(ws, A, A.ckpt0 + 2 * sg), L.bytes, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(F1, slot(ws, A, A.ckpt0 + 2 * sg + 1), L.bytes, hipMemcpyDeviceToDevice, s));
+        // the recompute reads the checkpoint pair in place (it stays intact
+        // for a later call) and sweeps on in F0 / F1
+        const SegLevels lv{slot(ws, A, A.ckpt0 + 2 * sg), slot(ws, A, A.ckpt0 + 2 * sg + 1), F0, F1};
         for (int64_t t = c; t < ce; t++) {
             ZView v{};
-            v.u = F0;
-            v.prev = F1;
-            v.out = F1;
+            v.u = lv.at(t - c);
+            v.prev = lv.at(t - c - 1);
+            v.out = lv.at(t - c + 1);
             v.beta = beta;
             v.g = L.g;
             v.dfield = (float*)slot(ws, A, A.seg0 + (t - c));
             set_tiling(v, L, var);
             v.src = fsrc;
-            HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, (int)((t - c) & 1), (int)t, -1, s));
+            HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t, -1, s));
         }
         // Adjoint step kk produces lambda at level kk-1 and images it with
         // the second difference of that level.  Steps go in pairs: a plain

@@ -143,3 +143,49 @@ def test_autograd_function_matches_direct_calls_and_fd(device):
     model(m0.detach())
     with pytest.raises(RuntimeError):
         (0.5 * (d3 ** 2).sum()).backward()
+
+
+@pytest.mark.parametrize("steps,every", [(40, 1), (41, 1), (41, 41), (41, 7), (40, 6), (40, 39)])
+def test_checkpointed_forward_equals_run_and_adjoint_repeats(device, steps, every):
+    """The checkpointed forward sweeps from checkpoint to checkpoint in the
+    workspace and into the caller's fields at the end: its final two levels
+    and traces equal the plain run's bit for bit, also when the workspace
+    starts filled with NaN bytes (only its interiors are ever written by the
+    sweeps), and a second adjoint call on the same checkpoints gives the same
+    gradient bits."""
+    import torch
+    P = _problem(shape=(26, 22, 34), steps=steps, seed=151)
+    dt, h = P["dt"], P["h"]
+    m0 = 1 / P["v0"] ** 2
+    plan = S.Plan(S.WAVE2, P["shape"], 4, S.second_derivative_weights(8), halo=4)
+    beta = W.round_to_storage(dt * dt / (h * h * m0), "f32")
+    amp = torch_f64((dt * dt / m0[tuple(P["src"][0])] * P["w"]).reshape(-1, 1), device)
+    nrec = len(P["rec"])
+
+    def fields():
+        f = [plan.field() for _ in range(3)]
+        f[2].load(W.embed(beta, 4))
+        return f
+
+    fr = fields()
+    tr_run = torch.zeros((steps, nrec), dtype=torch.float64, device=device)
+    plan.run(fr, steps, src=P["src"], src_amp=amp, rec=P["rec"], rec_trace=tr_run)
+    fc = fields()
+    tr = torch.zeros((steps, nrec), dtype=torch.float64, device=device)
+    ws = torch.full((plan.adjoint_workspace_bytes(steps, every),), 0xFF, dtype=torch.uint8, device=device)
+    plan.forward_ckpt(fc, steps, every, ws, src=P["src"], src_amp=amp, rec=P["rec"], rec_trace=tr)
+    torch.cuda.synchronize()
+    for i in (0, 1):
+        assert np.array_equal(fc[i].to_numpy().view(np.uint32), fr[i].to_numpy().view(np.uint32)), i
+    assert np.array_equal(tr.cpu().numpy(), tr_run.cpu().numpy())
+
+    resid = tr.clone()
+    scale = torch_f64(np.array([dt * dt / m0[tuple(p)] for p in P["rec"]]), device)
+    grads = []
+    for _ in range(2):
+        g = torch.zeros(P["shape"], dtype=torch.float64, device=device)
+        plan.adjoint(fc[2], steps, every, ws, resid, P["rec"], scale, dt, g, src=P["src"], src_amp=amp)
+        torch.cuda.synchronize()
+        grads.append(g.cpu().numpy())
+    assert np.all(np.isfinite(grads[0])) and np.any(grads[0] != 0)
+    assert np.array_equal(grads[0], grads[1])
