@@ -804,14 +804,17 @@ def bench_adjoint(S, W, steps, nsteps=500):
             gradient()
     ms_g = t.ms / steps
     pts = float(n) ** 3 * N
+    last = N - (N - 1) // k * k   # steps in the last checkpoint segment
     return {"interior": list(P.shape), "leapfrog_steps": N, "receivers": nrec, "checkpoint_every": k,
             "forward_GPts_s": round(pts / (ms_f * 1e-3) / 1e9, 2), "forward_ms": round(ms_f, 2),
             "gradient_GPts_s": round(pts / (ms_g * 1e-3) / 1e9, 2), "gradient_ms": round(ms_g, 2),
             "gradient_vs_forward_time": round(ms_g / ms_f, 3),
             "workspace_GB": round(ws.numel() / 1e9, 2),
-            # checkpointed forward 16 B, recompute with second differences
-            # 20 B, adjoint in pairs of steps 24 B (16 + 32 per pair)
-            "bytes_per_gradient_update": 60,
+            # checkpointed forward 16 B (20 B in its last segment, which
+            # also writes the second differences), recompute with second
+            # differences 20 B in every other segment, adjoint in pairs of
+            # steps 24 B (16 + 32 per pair)
+            "bytes_per_gradient_update": round(16 + 24 + (4 * last + 20 * (N - last)) / N, 2),
             "misfit": "J = 1/2 |d|^2 (d_obs = 0); timing only, parity is in the tests",
             "variant": plan.variant_name(plan.variant)}
 

@@ -186,22 +186,34 @@ __global__ void k_zero(uint32_t* p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
-// one block per row of the allocation (plane pz, row r); block `rows` clears
-// the tail past the last row
-__global__ void k_zero_frame(uint32_t* p, Grid3 g, int halo, int rows, int tail) {
-    const int q = blockIdx.x;
+// blockIdx.y: field f of `count` at `stride` elements from p; blockIdx.x:
+// plane pz of the allocation, or the tail past the last plane when pz equals
+// `planes`.  Halo planes are cleared whole, interior planes in their R halo
+// rows and, in the other rows, in the columns outside [xlead, xlead + n2).
+__global__ void k_zero_frame(uint32_t* p, int64_t stride, Grid3 g, int halo, int planes, int tail) {
+    const int pz = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int64_t s0 = g.s[0];
     const int rowlen = (int)g.rowlen;
-    uint32_t* row = p + (int64_t)q * rowlen;
-    if (q == rows) {
-        for (int c = threadIdx.x; c < tail; c += blockDim.x) row[c] = 0u;
+    uint32_t* const plane = p + (int64_t)blockIdx.y * stride + (int64_t)pz * s0;
+    if (pz == planes) {
+        for (int c = tid; c < tail; c += nt) plane[c] = 0u;
         return;
     }
-    const int ey = g.n[1] + 2 * halo;
-    const int pz = q / ey, r = q - pz * ey;
-    const bool frame = pz < halo || pz >= halo + g.n[0] || r < halo || r >= halo + g.n[1];
-    const int xb = (int)g.xlead, xe = xb + g.n[2];
-    for (int c = threadIdx.x; c < rowlen; c += blockDim.x)
-        if (frame || c < xb || c >= xe) row[c] = 0u;
+    if (pz < halo || pz >= halo + g.n[0]) {
+        uint4* const q = reinterpret_cast<uint4*>(plane);   // s0 is a multiple of 4, the plane 16-byte aligned
+        for (int64_t i = tid; i < s0 / 4; i += nt) q[i] = make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
+    uint32_t* const bottom = plane + (int64_t)(halo + g.n[1]) * rowlen;
+    for (int i = tid; i < halo * rowlen; i += nt) {
+        plane[i] = 0u;
+        bottom[i] = 0u;
+    }
+    const int xb = (int)g.xlead, xe = xb + g.n[2], npad = xb + rowlen - xe;
+    for (int i = tid; i < g.n[1] * npad; i += nt) {
+        const int r = i / npad, c = i - r * npad;
+        plane[(int64_t)(halo + r) * rowlen + (c < xb ? c : xe + (c - xb))] = 0u;
+    }
 }
 
 template <typename T>
@@ -213,14 +225,12 @@ __global__ void k_beta(const double* m, T* beta, Grid3 g, double scale) {
     Storage<T>::store(beta + g.origin + z * g.s[0] + y * g.s[1] + x, (float)(scale / m[q]));
 }
 
-__global__ void k_flush(float* g32, double* grad, Grid3 g, double scale) {
+__global__ void k_flush(const float* g32, double* grad, Grid3 g, double scale) {
     const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
     const int64_t x = q % g.n[2], y = (q / g.n[2]) % g.n[1], z = q / ((int64_t)g.n[2] * g.n[1]);
-    float* p = g32 + g.origin + z * g.s[0] + y * g.s[1] + x;
-    grad[q] += scale * (double)(*p);
-    *p = 0.f;
+    grad[q] += scale * (double)g32[g.origin + z * g.s[0] + y * g.s[1] + x];
 }
 
 // ----------------------------------------------------------- dispatchers
@@ -440,13 +450,17 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_zero_frame(void* p, const Grid3& g, int halo, int64_t elems, hipStream_t s) {
-    const int64_t rows = (int64_t)(g.n[0] + 2 * halo) * (g.n[1] + 2 * halo);
-    if (g.nd != 3 || g.s[1] != g.rowlen || g.s[0] != (g.n[1] + 2 * halo) * g.rowlen || rows * g.rowlen > elems ||
-        elems - rows * g.rowlen > 1024 || rows >= INT_MAX)
+hipError_t launch_zero_frame(void* p, int count, int64_t stride_bytes, const Grid3& g, int halo, int64_t elems,
+                             hipStream_t s) {
+    const int64_t planes = g.n[0] + 2 * (int64_t)halo;
+    const int64_t body = planes * g.s[0];
+    if (count <= 0) return hipSuccess;
+    if (g.nd != 3 || g.s[1] != g.rowlen || g.s[0] != (g.n[1] + 2 * halo) * g.rowlen || g.s[0] % 4 != 0 ||
+        body > elems || elems - body > 1024 || planes >= INT_MAX || stride_bytes % 16 != 0 ||
+        stride_bytes < elems * 4 || count > 65535 || (reinterpret_cast<uintptr_t>(p) & 15) != 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_zero_frame, dim3((unsigned)rows + 1), dim3(128), 0, s, (uint32_t*)p, g, halo, (int)rows,
-                       (int)(elems - rows * g.rowlen));
+    hipLaunchKernelGGL(k_zero_frame, dim3((unsigned)planes + 1, (unsigned)count), dim3(256), 0, s, (uint32_t*)p,
+                       stride_bytes / 4, g, halo, (int)planes, (int)(elems - body));
     return hipGetLastError();
 }
 
@@ -463,7 +477,7 @@ hipError_t launch_beta(int dtype, const double* m, void* beta, const Grid3& g, d
     return hipGetLastError();
 }
 
-hipError_t launch_flush(float* g32, double* grad, const Grid3& g, double scale, hipStream_t s) {
+hipError_t launch_flush(const float* g32, double* grad, const Grid3& g, double scale, hipStream_t s) {
     const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_flush, dim3(blocks_for(total, 256)), dim3(256), 0, s, g32, grad, g, scale);

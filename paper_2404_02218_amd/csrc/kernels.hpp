@@ -60,6 +60,7 @@ struct ZView {
     float* dfield;      // MODE_WAVE_D: written; MODE_WAVE_ADJ: read (same layout)
     float* gfield;      // MODE_WAVE_ADJ(2): imaging partial (same layout)
     const float* dfield2;  // MODE_WAVE_ADJ2: the second difference paired with the input level u
+    int gfresh;            // MODE_WAVE_ADJ(2): the partial starts at zero (gfield is not read)
     const float* damp;  // MODE_WAVE_DAMP: per-axis damping [n0 | n1 | n2], gamma = (d0 + d1) + d2
     Grid3 g;
     int ntx, nty, zc, nzc;  // z-marching tiling: tiles along x, y; z-chunk length and count
@@ -222,12 +223,14 @@ hipError_t launch_record(int dtype, const void* base, const Grid3& g, const RecL
 hipError_t launch_boxcopy(int dtype, int dir, void* field, const Grid3& g, int64_t offset, const CopyList& L,
                           void* buf, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
-// zero every 32-bit element of a 3D FP32 field allocation of `elems`
-// elements except its interior (halo planes, rows and columns, the row
-// padding and the tail), so that a sweep can write into it as its output
-hipError_t launch_zero_frame(void* p, const Grid3& g, int halo, int64_t elems, hipStream_t s);
+// zero every 32-bit element of `count` 3D FP32 field allocations of `elems`
+// elements, stride_bytes apart from p, except their interiors (halo planes,
+// rows and columns, the row padding and the tail), so that a sweep can write
+// into them as its output
+hipError_t launch_zero_frame(void* p, int count, int64_t stride_bytes, const Grid3& g, int halo, int64_t elems,
+                             hipStream_t s);
 hipError_t launch_beta(int dtype, const double* m, void* beta, const Grid3& g, double scale, hipStream_t s);
-hipError_t launch_flush(float* g32, double* grad, const Grid3& g, double scale, hipStream_t s);
+hipError_t launch_flush(const float* g32, double* grad, const Grid3& g, double scale, hipStream_t s);
 
 // checks.hip: out[i] = dt2 / m[off[i]]; the data residual and its misfit
 // 1/2 |trace - dobs|^2 (one workgroup, a fixed summation order); the scan of

@@ -265,6 +265,11 @@ struct stencil_plan_s {
     // stencil_gradient: source and receiver scales, residual; stencil_check:
     // NaN and infinity counts and the largest magnitude's bits
     DevBuf gsrc_scale, grec_scale, gresid, scan;
+    // the workspace whose second-difference slots hold the last segment's
+    // levels, written by the checkpointed forward (cleared once a recompute
+    // overwrites them), with that forward's step count and interval
+    const void* last_seg_ws = nullptr;
+    int64_t last_seg_nsteps = 0, last_seg_k = 0;
     // interpolated sources and receivers (stencil_run_interp): corner
     // weights, the corners' amplitudes and the corner trace
     DevTable interp_sw, interp_rw;
@@ -2179,8 +2184,9 @@ static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t n
     // for odd N, as the plain run leaves them).
     HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0), a, L.bytes, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot(ws, A, A.ckpt0 + 1), b, L.bytes, hipMemcpyDeviceToDevice, s));
-    for (int64_t c = 2; c < 2 * A.nseg; c++)
-        HIP_TRY(launch_zero_frame(slot(ws, A, A.ckpt0 + c), L.g, L.halo, L.elems, s));
+    for (int64_t c0 = 2; c0 < 2 * A.nseg; c0 += 65535)
+        HIP_TRY(launch_zero_frame(slot(ws, A, A.ckpt0 + c0), (int)std::min<int64_t>(65535, 2 * A.nseg - c0), A.fbytes,
+                                  L.g, L.halo, L.elems, s));
     for (int64_t c = 0; c < A.nseg; c++) {
         const int64_t t0 = c * k, len = std::min(t0 + k, nsteps) - t0;
         const bool last = c + 1 == A.nseg;
@@ -2189,6 +2195,8 @@ static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t n
         void* const tu = last ? ((nsteps & 1) ? b : a) : slot(ws, A, A.ckpt0 + 2 * c + 2);
         void* const tp = last ? ((nsteps & 1) ? a : b) : slot(ws, A, A.ckpt0 + 2 * c + 3);
         const SegLevels lv{cur, prv, (len & 1) ? tp : tu, (len & 1) ? tu : tp};
+        // the last segment also writes its second differences, which the
+        // adjoint then takes without recomputing that segment
         for (int64_t j = 0; j < len; j++) {
             const int64_t t = t0 + j;
             ZView v{};
@@ -2197,10 +2205,11 @@ static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t n
             v.out = lv.at(j + 1);
             v.beta = fields[2];
             v.g = L.g;
+            if (last) v.dfield = (float*)slot(ws, A, A.seg0 + j);
             set_tiling(v, L, var);
             v.src = sl;
             v.rec = rl;
-            HIP_TRY(launch_zmarch(MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t,
+            HIP_TRY(launch_zmarch(last ? MODE_WAVE_D : MODE_WAVE, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t,
                                   (rl.n > 0 && t >= 1) ? (int)(t - 1) : -1, s));
         }
         // one-step segment: u^{t0} is still only in pair c
@@ -2208,6 +2217,9 @@ static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t n
     }
     if (rl.n > 0) HIP_TRY(launch_record(p->dtype, (nsteps & 1) ? b : a, L.g, rl, (int)(nsteps - 1), s));
     if (nsteps & 1) std::swap(fields[0], fields[1]);
+    p->last_seg_ws = ws;
+    p->last_seg_nsteps = nsteps;
+    p->last_seg_k = k;
     return STENCIL_OK;
 }
 
@@ -2231,26 +2243,30 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
     float* G = (float*)slot(ws, A, A.g);
     HIP_TRY(launch_zero(L0, L.bytes, s));
     HIP_TRY(launch_zero(L1, L.bytes, s));
-    HIP_TRY(launch_zero(G, L.bytes, s));
-    HIP_TRY(launch_zero_frame(F0, L.g, L.halo, L.elems, s));
-    HIP_TRY(launch_zero_frame(F1, L.g, L.halo, L.elems, s));
+    HIP_TRY(launch_zero_frame(F0, 2, A.fbytes, L.g, L.halo, L.elems, s));   // F0 and F1 (adjacent slots)
+    const bool have_last = p->last_seg_ws == ws && p->last_seg_nsteps == nsteps && p->last_seg_k == k;
     int64_t j = 0;  // adjoint steps taken (parity of the lambda buffers)
     for (int64_t sg = A.nseg - 1; sg >= 0; sg--) {
         const int64_t c = sg * k, ce = std::min(c + k, nsteps);
-        // the recompute reads the checkpoint pair in place (it stays intact
-        // for a later call) and sweeps on in F0 / F1
-        const SegLevels lv{slot(ws, A, A.ckpt0 + 2 * sg), slot(ws, A, A.ckpt0 + 2 * sg + 1), F0, F1};
-        for (int64_t t = c; t < ce; t++) {
-            ZView v{};
-            v.u = lv.at(t - c);
-            v.prev = lv.at(t - c - 1);
-            v.out = lv.at(t - c + 1);
-            v.beta = beta;
-            v.g = L.g;
-            v.dfield = (float*)slot(ws, A, A.seg0 + (t - c));
-            set_tiling(v, L, var);
-            v.src = fsrc;
-            HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t, -1, s));
+        // the last segment's second differences may still be there from
+        // the checkpointed forward
+        if (sg != A.nseg - 1 || !have_last) {
+            p->last_seg_ws = nullptr;
+            // the recompute reads the checkpoint pair in place (it stays intact
+            // for a later call) and sweeps on in F0 / F1
+            const SegLevels lv{slot(ws, A, A.ckpt0 + 2 * sg), slot(ws, A, A.ckpt0 + 2 * sg + 1), F0, F1};
+            for (int64_t t = c; t < ce; t++) {
+                ZView v{};
+                v.u = lv.at(t - c);
+                v.prev = lv.at(t - c - 1);
+                v.out = lv.at(t - c + 1);
+                v.beta = beta;
+                v.g = L.g;
+                v.dfield = (float*)slot(ws, A, A.seg0 + (t - c));
+                set_tiling(v, L, var);
+                v.src = fsrc;
+                HIP_TRY(launch_zmarch(MODE_WAVE_D, p->radius, p->dtype, var.cfg, v, p->w, 0, (int)t, -1, s));
+            }
         }
         // Adjoint step kk produces lambda at level kk-1 and images it with
         // the second difference of that level.  Steps go in pairs: a plain
@@ -2258,6 +2274,7 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
         // and its output, so the partial G is read and written once per two
         // steps with the same roundings in the same order.  An odd remainder
         // takes the one-level imaging step.
+        bool fresh = true;   // the segment's first imaging step starts the partial at zero
         for (int64_t kk = ce; kk > c;) {
             ZView v{};
             v.u = L0;
@@ -2273,6 +2290,8 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
                 v.dfield2 = (const float*)slot(ws, A, A.seg0 + (kk - 1 - c));
                 v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 2 - c));
                 v.gfield = G;
+                v.gfresh = fresh;
+                fresh = false;
                 HIP_TRY(launch_zmarch(MODE_WAVE_ADJ2, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 2), -1,
                                       s));
                 j++;
@@ -2280,6 +2299,8 @@ static stencil_status adjoint_impl(stencil_plan p, const void* beta, int64_t nst
             } else {
                 v.dfield = (float*)slot(ws, A, A.seg0 + (kk - 1 - c));
                 v.gfield = G;
+                v.gfresh = fresh;
+                fresh = false;
                 HIP_TRY(launch_zmarch(MODE_WAVE_ADJ, p->radius, p->dtype, var.cfg, v, p->w, (int)(j & 1), (int)(kk - 1), -1, s));
                 j++;
                 kk -= 1;

@@ -302,10 +302,12 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // adjoint: D and G of this thread's groups that lie wholly inside the
     // interior, at the current plane; like u_prev and beta they are loaded a
     // plane ahead, so their latency overlaps the compute (other groups read
-    // them at the store)
+    // them at the store); with gfresh the partial starts at zero and is not
+    // read
     bool dg_ok[VY];
     int64_t dg_off[VY];
     float4 cd[VY][NV], cg[VY][NV], cd2[VY][NV];
+    const bool gload = ADJ && !v.gfresh;
     if constexpr (ADJ) {
 #pragma unroll
         for (int j = 0; j < VY; j++) {
@@ -316,7 +318,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
                 for (int c = 0; c < NV; c++) {
                     cd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
-                    cg[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + (int64_t)zb * sz + 4 * c);
+                    cg[j][c] = gload ? Storage<float>::load4_nt(v.gfield + dg_off[j] + (int64_t)zb * sz + 4 * c)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
                     if constexpr (ADJ2)
                         cd2[j][c] = Storage<float>::load4_nt(v.dfield2 + dg_off[j] + (int64_t)zb * sz + 4 * c);
                 }
@@ -417,7 +420,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
                         for (int c = 0; c < NV; c++) {
                             nd[j][c] = Storage<float>::load4_nt(v.dfield + dg_off[j] + zn + 4 * c);
-                            ng[j][c] = Storage<float>::load4_nt(v.gfield + dg_off[j] + zn + 4 * c);
+                            ng[j][c] = gload ? Storage<float>::load4_nt(v.gfield + dg_off[j] + zn + 4 * c)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
                             if constexpr (ADJ2) nd2[j][c] = Storage<float>::load4_nt(v.dfield2 + dg_off[j] + zn + 4 * c);
                         }
                     }
@@ -633,7 +637,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
 #pragma unroll
                         for (int i = 0; i < VX; i++)
                             if (x0 + i < nx) {
-                                float g = G[i];
+                                float g = gload ? G[i] : 0.f;
                                 if constexpr (ADJ2) g = fmaf(comp(qi(R)[j][i / 4], i % 4), D2[i], g);
                                 G[i] = fmaf(o[j][i], D[i], g);
                             }
