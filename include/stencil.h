@@ -333,7 +333,10 @@ stencil_status stencil_adjoint_workspace(stencil_plan plan, int64_t nsteps, int6
 
 /* Forward run of the adjoint path (the Section 6.1 wave sweep as
  * stencil_run, fields = {u_n, u_prev, beta}), also storing (u^c, u^{c-1})
- * for c = 0, k, 2k, ... into the workspace. */
+ * for c = 0, k, 2k, ... into the workspace (the sweeps write them there
+ * directly) and the last segment's second differences, which the plan
+ * notes for the next stencil_adjoint on the same workspace, nsteps and
+ * checkpoint_every. */
 stencil_status stencil_forward_ckpt(stencil_plan plan, void** fields, int64_t nsteps,
                                     int64_t checkpoint_every, const stencil_source* src,
                                     const stencil_receivers* rec, void* workspace,
@@ -346,7 +349,11 @@ stencil_status stencil_forward_ckpt(stencil_plan plan, void** fields, int64_t ns
  *   grad += -(1/dt^2) sum_n lam^n .* (u^{n+1} - 2u^n + u^{n-1}).
  * The forward levels are recomputed segment by segment from the checkpoints
  * left in `workspace` by stencil_forward_ckpt with the same nsteps,
- * checkpoint_every, beta and sources.  For J = 1/2 |d - d_obs|^2:
+ * checkpoint_every, beta and sources (the last segment's second
+ * differences are taken from that forward when this plan's last
+ * checkpointed forward used this workspace and no adjoint has recomputed
+ * since).  The checkpoints are left intact: a second call on the same
+ * workspace gives the same result.  For J = 1/2 |d - d_obs|^2:
  * resid = d - d_obs and rec_scale = dt^2 / m_r (stencil_wave_point_scale).
  * The forward and this backward are separate calls so that a caller can
  * drive the backward with any trace gradient (torch.autograd); see
