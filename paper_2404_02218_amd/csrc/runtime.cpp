@@ -1897,7 +1897,16 @@ static stencil_status ensure_branches(stencil_plan p) {
     return STENCIL_OK;
 }
 
-// shots to branches, largest first, each to the branch with the least work
+// Shots with at least this many points fill the GPU on their own (about
+// 32K points per compute unit).
+constexpr int64_t kLargeShotPoints = int64_t(1) << 23;
+
+// Shots to branches.  The large shots run one after another on the first
+// branch, largest first, as the sequential runs do; the others are dealt
+// largest first to the least-loaded of the remaining branches, where their
+// launches take the compute units a large shot's launch leaves idle.  (Large
+// shots spread over several branches compete for the caches and run slower
+// than one after another.)  Without large shots every branch takes small ones.
 static std::vector<std::vector<int>> branch_lists(const stencil_plan_s* p) {
     const int ns = (int)p->shots.size();
     std::vector<int> order(ns);
@@ -1908,15 +1917,17 @@ static std::vector<std::vector<int>> branch_lists(const stencil_plan_s* p) {
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
     std::vector<std::vector<int>> lists(kBranches);
+    const int first_small = ns > 0 && work(order[0]) >= kLargeShotPoints ? 1 : 0;
     std::vector<int64_t> load(kBranches, 0);
     for (int i : order) {
-        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        if (work(i) >= kLargeShotPoints) {
+            lists[0].push_back(i);
+            continue;
+        }
+        const int b = (int)(std::min_element(load.begin() + first_small, load.end()) - load.begin());
         load[b] += work(i);
         lists[b].push_back(i);
     }
-    // every other branch runs its shots smallest first, so that large and
-    // small shots share the GPU through the run
-    for (int b = 1; b < kBranches; b += 2) std::reverse(lists[b].begin(), lists[b].end());
     return lists;
 }
 
