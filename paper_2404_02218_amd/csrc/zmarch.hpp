@@ -299,6 +299,31 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         }
     }
 
+    // Prefetch distance 2 (forward sweeps of 16-bit fields, 8 points per
+    // lane): plane zb + 1's loads are pending before the first plane, and each
+    // plane issues plane z + 2's, so two planes of loads are in flight.  With
+    // 16-byte loads of 16-bit values a plane's loads are half the bytes of
+    // the FP32 form's; the second plane brings the bytes in flight back up
+    // (512^3 BF16: 246 -> 210 us per sweep).  Other shapes and FP32 gain
+    // nothing or lose, and keep distance 1.
+    constexpr bool PD2 = DEFER && kLds16<T> && VX == 8;
+    Raw pq[VY][NV], pp[VY][NV], pb[VY][NV], phal[NH];
+    if constexpr (PD2) {
+        const int64_t z1 = (int64_t)min(zb + 1, ze - 1) * sz;
+#pragma unroll
+        for (int j = 0; j < VY; j++) load_vec_raw<T, VX, false>(U + z1 + (int64_t)R * sz + own[j], pq[j]);
+#pragma unroll
+        for (int m = 0; m < NH; m++)
+            if (hon[m]) phal[m] = load4_raw<T, false>(U + z1 + (int64_t)R * sz + hoff[m]);
+        if constexpr (WAVE) {
+#pragma unroll
+            for (int j = 0; j < VY; j++) {
+                load_vec_raw<T, VX, NTH>(P + z1 + own[j], pp[j]);
+                load_vec_raw<T, VX, NTH>(B + z1 + own[j], pb[j]);
+            }
+        }
+    }
+
     // adjoint: D and G of this thread's groups that lie wholly inside the
     // interior, at the current plane; like u_prev and beta they are loaded a
     // plane ahead, so their latency overlaps the compute (other groups read
@@ -395,7 +420,22 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         const bool more = z + 1 < ze;
         Raw np[VY][NV], nb[VY][NV];
         float4 nd[VY][NV], ng[VY][NV], nd2[VY][NV];
-        if (DEFER || more) {
+        Raw n2q[VY][NV], n2p[VY][NV], n2b[VY][NV], n2h[NH];
+        if constexpr (PD2) {
+            const int64_t zn2 = (int64_t)min(z + 2, ze - 1) * sz;
+#pragma unroll
+            for (int j = 0; j < VY; j++) load_vec_raw<T, VX, false>(U + zn2 + (int64_t)R * sz + own[j], n2q[j]);
+#pragma unroll
+            for (int m = 0; m < NH; m++)
+                if (hon[m]) n2h[m] = load4_raw<T, false>(U + zn2 + (int64_t)R * sz + hoff[m]);
+            if constexpr (WAVE) {
+#pragma unroll
+                for (int j = 0; j < VY; j++) {
+                    load_vec_raw<T, VX, NTH>(P + zn2 + own[j], n2p[j]);
+                    load_vec_raw<T, VX, NTH>(B + zn2 + own[j], n2b[j]);
+                }
+            }
+        } else if (DEFER || more) {
             // DEFER: past the chunk the loads re-read the current plane's
             // rows (in the field; the values go unused)
             const int64_t zn = (int64_t)(more ? z + 1 : z) * sz;
@@ -646,7 +686,43 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             }
         }
 
-        if (more) {
+        if constexpr (PD2) {
+            if (more) {
+#pragma unroll
+                for (int j = 0; j < VY; j++)
+#pragma unroll
+                    for (int c = 0; c < NV; c++) {
+                        if constexpr (MIX) {
+                            q[OFF][j][c] = pq[j][c];
+                            if constexpr (WAVE) {
+                                cp[j][c] = pp[j][c];
+                                cb[j][c] = pb[j][c];
+                            }
+                        } else {
+                            q[OFF][j][c] = widen4<T>(pq[j][c]);
+                            if constexpr (WAVE) {
+                                cp[j][c] = widen4<T>(pp[j][c]);
+                                cb[j][c] = widen4<T>(pb[j][c]);
+                            }
+                        }
+                    }
+            }
+#pragma unroll
+            for (int m = 0; m < NH; m++) {
+                hal[m] = phal[m];
+                phal[m] = n2h[m];
+            }
+#pragma unroll
+            for (int j = 0; j < VY; j++)
+#pragma unroll
+                for (int c = 0; c < NV; c++) {
+                    pq[j][c] = n2q[j][c];
+                    if constexpr (WAVE) {
+                        pp[j][c] = n2p[j][c];
+                        pb[j][c] = n2b[j][c];
+                    }
+                }
+        } else if (more) {
 #pragma unroll
             for (int j = 0; j < VY; j++)
 #pragma unroll
