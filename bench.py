@@ -349,7 +349,8 @@ def bench_batch(S, W, steps, nsteps=200, only_variant=None):
     names = {bp.variant_name(v): v for v in range(1, bp.variant_count())}
     per_variant = {bp.variant_name(tuned): round(ms_b, 2)}
     for name in ("shots_concurrent_4", "tb2_64x32_t768_zc128", "tb2_64x32_t768_zc256", "zmarch_64x16_t256_zc32_nt",
-                 "zmarch_64x16_t256_zc128_nt", "zmarch_64x16_t256_zc256_nt"):
+                 "zmarch_64x16_t256_zc128_nt", "zmarch_64x16_t256_zc256_nt", "persistent_zmarch_64x16_t256_zc32_nt",
+                 "persistent_zmarch_64x16_t256_zc128_nt", "persistent_zmarch_64x16_t256_zc256_nt"):
         if name in names and name not in per_variant:
             bp.variant = names[name]
             run_batch()

@@ -313,6 +313,32 @@ hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_vi
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_zmarch_batch_persistent(int radius, int dtype, int cfg, const ZView* d_views, const int* d_list,
+                                          const int* d_off, int grid, const Coefs& w, int t0, int t1, int rec_on,
+                                          int pmask, unsigned long long* d_sync, int spin_limit, hipStream_t s) {
+    switch (dtype) {
+        case DT_F32:
+            return zmarch_batch_persistent_f32(radius, cfg, d_views, d_list, d_off, grid, w, t0, t1, rec_on, pmask,
+                                               d_sync, spin_limit, s);
+        case DT_BF16:
+            return zmarch_batch_persistent_bf16(radius, cfg, d_views, d_list, d_off, grid, w, t0, t1, rec_on, pmask,
+                                                d_sync, spin_limit, s);
+        case DT_F16:
+            return zmarch_batch_persistent_f16(radius, cfg, d_views, d_list, d_off, grid, w, t0, t1, rec_on, pmask,
+                                               d_sync, spin_limit, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t zmarch_batch_persistent_per_cu(int radius, int dtype, int cfg, int* per_cu) {
+    switch (dtype) {
+        case DT_F32: return zmarch_batch_persistent_per_cu_f32(radius, cfg, per_cu);
+        case DT_BF16: return zmarch_batch_persistent_per_cu_bf16(radius, cfg, per_cu);
+        case DT_F16: return zmarch_batch_persistent_per_cu_f16(radius, cfg, per_cu);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_inject(int dtype, void* out_base, const Grid3& g, const SrcList& src, int arow, hipStream_t s) {
     if (src.ngrp == 0) return hipSuccess;
     const unsigned nb = blocks_for(src.ngrp, 64);

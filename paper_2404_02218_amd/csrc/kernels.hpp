@@ -143,6 +143,10 @@ inline constexpr TileCfg kTileCfgs[] = {
     {16, 16, 1, 4, false},  // 64 x 16 tile, 256 threads
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
+// the tile shape of the persistent batched sweep (64 x 16, streaming hints)
+inline constexpr int kPersistentCfg = 1;
+// 64-bit words of its barrier, error flag and per-XCD ticket counters
+inline constexpr int kPersistentWords = 2 + 2 * 8;
 // z-chunk lengths of the z-marching variants
 inline constexpr int kZChunks[] = {256, 128, 64, 32};
 inline constexpr int kNumZChunks = sizeof(kZChunks) / sizeof(kZChunks[0]);
@@ -174,6 +178,19 @@ hipError_t launch_zmarch(int mode, int radius, int dtype, int cfg, const ZView& 
 // batched shots: d_block_map[2 b], d_block_map[2 b + 1] = shot and block within the shot of block b
 hipError_t launch_zmarch_batch(int radius, int dtype, int cfg, const ZView* d_views, const int* d_block_map,
                                int nblocks, const Coefs& w, int parity, int arow, int trow, hipStream_t s);
+// batched shots, steps t0 .. t1 - 1 in one persistent launch of `grid`
+// workgroups (that the GPU holds at once); the (shot, block) pairs of XCD x
+// are d_list[d_qoff[x]] .. d_list[d_qoff[x + 1] - 1] (8 queues, each in map
+// order); step t has parity t & pmask, amplitude row t and, with rec_on,
+// trace row t - 1.  d_sync: kPersistentWords zeroed words (barrier
+// count, error flag, ticket counters; the flag is nonzero after the launch
+// if a barrier wait gave up after spin_limit polls).  Radius 4, the 64 x 16
+// streaming tile only.
+hipError_t launch_zmarch_batch_persistent(int radius, int dtype, int cfg, const ZView* d_views, const int* d_list,
+                                          const int* d_qoff, int grid, const Coefs& w, int t0, int t1, int rec_on,
+                                          int pmask, unsigned long long* d_sync, int spin_limit, hipStream_t s);
+// workgroups of that kernel one compute unit holds at once
+hipError_t zmarch_batch_persistent_per_cu(int radius, int dtype, int cfg, int* per_cu);
 // per-storage-type instantiations (zmarch_*.hip)
 hipError_t zmarch_fwd_f32(int mode, int radius, int cfg, const ZView& v, const Coefs& w, int parity, int arow,
                           int trow, hipStream_t s);
@@ -189,6 +206,18 @@ hipError_t zmarch_batch_bf16(int radius, int cfg, const ZView* views, const int*
                              int parity, int arow, int trow, hipStream_t s);
 hipError_t zmarch_batch_f16(int radius, int cfg, const ZView* views, const int* bmap, int nblocks, const Coefs& w,
                             int parity, int arow, int trow, hipStream_t s);
+hipError_t zmarch_batch_persistent_f32(int radius, int cfg, const ZView* views, const int* list, const int* off, int grid,
+                                      const Coefs& w, int t0, int t1, int rec_on, int pmask, unsigned long long* sync,
+                                      int spin_limit, hipStream_t s);
+hipError_t zmarch_batch_persistent_per_cu_f32(int radius, int cfg, int* per_cu);
+hipError_t zmarch_batch_persistent_bf16(int radius, int cfg, const ZView* views, const int* list, const int* off, int grid,
+                                      const Coefs& w, int t0, int t1, int rec_on, int pmask, unsigned long long* sync,
+                                      int spin_limit, hipStream_t s);
+hipError_t zmarch_batch_persistent_per_cu_bf16(int radius, int cfg, int* per_cu);
+hipError_t zmarch_batch_persistent_f16(int radius, int cfg, const ZView* views, const int* list, const int* off, int grid,
+                                      const Coefs& w, int t0, int t1, int rec_on, int pmask, unsigned long long* sync,
+                                      int spin_limit, hipStream_t s);
+hipError_t zmarch_batch_persistent_per_cu_f16(int radius, int cfg, int* per_cu);
 // Depth-2 temporal blocking.  Wave (radius 4): steps arow and arow + 1;
 // receivers record u^n as row trow_u and u^{n-1} as row trow_p (if >= 0).
 // Heat (radius 1..4, FP32): u^{n+2} from u^n into out2.

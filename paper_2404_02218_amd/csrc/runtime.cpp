@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -160,11 +161,17 @@ struct DevTable {
 struct Variant {
     bool zmarch = false;
     bool tb = false;   // depth-2 temporal blocking (tile 64 x 32 = tile shape 0)
+    bool persistent = false;   // batch: every step in one launch with grid barriers
     int cfg = 0;
     int zc = 0;
 };
 
 constexpr int kNumZVariants = kNumTileCfgs * kNumZChunks;
+// batch plans: persistent launches on the 64 x 16 streaming tile, one per
+// z-chunk length
+constexpr int kNumPersistent = kNumZChunks;
+// steps of one tuning launch of a persistent variant
+constexpr int kPersistentTuneSteps = 4;
 // branches of the concurrent batch variant: the hardware queues a process
 // gets by default
 constexpr int kBranches = 4;
@@ -298,6 +305,13 @@ struct stencil_plan_s {
     std::vector<stencil_plan_s*> shot_plans;
     hipStream_t branch[kBranches] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {};
+    // the persistent batch variants: the barrier count and error flag
+    // (device), the flag read back (pinned host), and the grid
+    DevBuf bsync;
+    unsigned long long* bsync_host = nullptr;
+    int pgrid = 0;
+    DevTable plist, poff;       // the per-XCD queues (entries, offsets)
+    std::vector<int> hmap;      // the block map on the host
     // stencil program
     int nin = 0, nout = 0, reach[3] = {0, 0, 0};
     std::vector<ProgTerm> pterms;
@@ -314,6 +328,7 @@ struct stencil_plan_s {
         if (fork_ev) (void)hipEventDestroy(fork_ev);
         for (hipEvent_t e : join_ev)
             if (e) (void)hipEventDestroy(e);
+        if (bsync_host) (void)hipHostFree(bsync_host);
     }
 };
 
@@ -354,13 +369,31 @@ int variant_count_of(const stencil_plan_s* p) {
         return 3 + (program_rtc_lds_bytes(p->nin, p->reach[0], p->reach[1], false, 2 * kProgTileY) <= kLdsPerCu);
     // batch: z-marching and temporally blocked launches over all shots, then
     // the concurrent per-shot runs
-    if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0) + 1;
+    if (p->batch) return kNumZVariants + 1 + (tb_batch_supported(p) ? kNumTB2ZChunks : 0) + kNumPersistent + 1;
     if (p->ndim != 3) return heat2d_supported(p) ? 1 + kNumHeat2dCfgs : 1;
     return 1 + kNumZVariants + (tb_supported(p) ? kNumTB2ZChunks : 0);
 }
 
 // the batch variant that runs every shot with its own plan, concurrently
 bool batch_concurrent(const stencil_plan_s* p, int v) { return p->batch && v == variant_count_of(p) - 1; }
+
+// the batch variants that run every step in one persistent launch (just
+// before the concurrent one)
+bool batch_persistent(const stencil_plan_s* p, int v) {
+    const int n = variant_count_of(p);
+    return p->batch && v >= n - 1 - kNumPersistent && v < n - 1;
+}
+
+// variant v of plan p (batch plans add the persistent launches)
+Variant plan_variant(const stencil_plan_s* p, int v) {
+    if (!batch_persistent(p, v)) return variant_of(v);
+    Variant r;
+    r.zmarch = true;
+    r.persistent = true;
+    r.cfg = kPersistentCfg;
+    r.zc = kZChunks[v - (variant_count_of(p) - 1 - kNumPersistent)];
+    return r;
+}
 
 // plans of the sweep entry points (not stencil programs)
 stencil_status check_sweep_plan(stencil_plan p) {
@@ -1080,7 +1113,7 @@ static size_t run_workspace_bytes(const stencil_plan_s* p) {
         for (const stencil_plan_s* q : p->shot_plans) b += run_workspace_bytes(q);
         return b;
     }
-    const Variant var = variant_of(p->variant);
+    const Variant var = plan_variant(p, p->variant);
     if (!var.tb) return 0;
     if (p->batch) {
         size_t b = 0;
@@ -1723,7 +1756,7 @@ stencil_status stencil_batch_layout(stencil_plan p, int shot, int64_t* extents, 
 // XCD with the least work so far, largest groups first, and each XCD's list
 // is padded to the longest.  Work of a group = tiles x (chunk planes + 2r).
 static stencil_status build_block_map_impl(const std::vector<ZView>& views, const std::vector<int>& nz, int radius,
-                                           DevTable& table, int& nblocks) {
+                                           DevTable& table, int& nblocks, std::vector<int>* host_map = nullptr) {
     constexpr int kXcds = 8;
     struct Group {
         int shot, chunk, tiles;
@@ -1761,7 +1794,27 @@ static stencil_status build_block_map_impl(const std::vector<ZView>& views, cons
             map[2 * b] = lists[x][2 * i];
             map[2 * b + 1] = lists[x][2 * i + 1];
         }
+    if (host_map) *host_map = map;
     return table.upload(map.data(), sizeof(int) * map.size());
+}
+
+// The persistent batched sweep's queues: queue x holds the map's entries of
+// XCD x (map index b with b % 8 == x, the pads dropped) in map order.
+// list: (shot, block) pairs, qoff: 9 offsets.
+static stencil_status build_persistent_queues(const std::vector<int>& map, DevTable& list, DevTable& qoff) {
+    constexpr int kXcds = 8;
+    std::vector<int> l, o(kXcds + 1, 0);
+    for (int x = 0; x < kXcds; x++) {
+        for (size_t b = x; 2 * b < map.size(); b += kXcds) {
+            if (map[2 * b] < 0) continue;
+            l.push_back(map[2 * b]);
+            l.push_back(map[2 * b + 1]);
+        }
+        o[x + 1] = (int)(l.size() / 2);
+    }
+    if (l.empty()) l.assign(2, 0);
+    ST_TRY(list.upload(l.data(), sizeof(int) * l.size()));
+    return qoff.upload(o.data(), sizeof(int) * o.size());
 }
 
 static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nsteps, const stencil_source* src,
@@ -1797,7 +1850,7 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
     {
         std::vector<int> nz(ns);
         for (int s = 0; s < ns; s++) nz[s] = p->shots[s].g.n[0];
-        ST_TRY(build_block_map_impl(views, nz, p->radius, p->block_map, p->nblocks));
+        ST_TRY(build_block_map_impl(views, nz, p->radius, p->block_map, p->nblocks, &p->hmap));
     }
     if (var.tb) {
         // pass k reads pair k & 1 (newest, previous) and writes the other pair
@@ -1833,11 +1886,65 @@ static stencil_status batch_prepare(stencil_plan p, void** fields, int64_t nstep
     return STENCIL_OK;
 }
 
+// Polls a waiting workgroup makes at a persistent launch's grid barrier
+// before it gives up: 2^20 polls, each a device-coherent load and a short
+// sleep (about a microsecond or more), so about a second, against a few
+// milliseconds for one step of the largest batch that fits in HBM.
+// STENCIL_BARRIER_POLLS overrides it (the tests force the error path with 0).
+static int barrier_polls() {
+    const char* e = std::getenv("STENCIL_BARRIER_POLLS");
+    if (e && *e) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 0 && v <= (1L << 30)) return (int)v;
+    }
+    return 1 << 20;
+}
+
+// The persistent variants' grid: every map entry's workgroup if the GPU holds
+// them all at once, else as many as it holds, rounded down to a multiple of
+// 8 (each then takes several entries per step); the barrier words and the
+// pinned flag on first use.
+static stencil_status prepare_persistent(stencil_plan p, const Variant& var, const std::vector<int>& map, int nmap,
+                                         DevTable& list, DevTable& qoff) {
+    int per_cu = 0, dev = 0, cus = 0;
+    HIP_TRY(zmarch_batch_persistent_per_cu(p->radius, p->dtype, var.cfg, &per_cu));
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t resident = (int64_t)per_cu * cus / 8 * 8;
+    if (resident < 8) return fail(STENCIL_E_DEVICE, "the persistent batched sweep does not fit 8 workgroups on the GPU");
+    p->pgrid = (int)std::min<int64_t>(nmap, resident);
+    ST_TRY(build_persistent_queues(map, list, qoff));
+    ST_TRY(p->bsync.ensure(kPersistentWords * sizeof(unsigned long long)));
+    if (!p->bsync_host) HIP_TRY(hipHostMalloc((void**)&p->bsync_host, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+    return STENCIL_OK;
+}
+
+// After a persistent launch: wait for it and report a barrier that gave up.
+static stencil_status check_persistent(stencil_plan p, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(p->bsync_host, p->bsync.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (p->bsync_host[1] != 0)
+        return fail(STENCIL_E_DEVICE, "persistent batched sweep: a grid barrier gave up waiting (the grid of " +
+                                          std::to_string(p->pgrid) +
+                                          " workgroups was not resident at once); the fields are not valid");
+    return STENCIL_OK;
+}
+
 static stencil_status enqueue_batch(stencil_plan p, const std::vector<ZView>& views, int64_t nsteps, const Variant& var,
                                     bool any_rec, hipStream_t s) {
     const int ns = (int)p->shots.size();
     const int nblocks = p->nblocks;
     int64_t t0 = 0;
+    if (var.persistent) {
+        // every step in one launch (the barrier words start at zero: a fill
+        // kernel, which a graph replays correctly)
+        HIP_TRY(launch_zero(p->bsync.p, kPersistentWords * sizeof(unsigned long long), s));
+        HIP_TRY(launch_zmarch_batch_persistent(p->radius, p->dtype, var.cfg, (const ZView*)p->views.buf.p,
+                                               (const int*)p->plist.buf.p, (const int*)p->poff.buf.p, p->pgrid, p->w,
+                                               0, (int)nsteps, any_rec ? 1 : 0, 1, (unsigned long long*)p->bsync.p,
+                                               barrier_polls(), s));
+        t0 = nsteps;
+    }
     if (var.tb) {
         // an even number of two-step passes (as in a single-plan run), then
         // plain batched sweeps on the 64 x 32 tiles for the rest
@@ -2051,7 +2158,7 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
     ST_TRY(check_workspace(p));
     hipStream_t s = (hipStream_t)stream;
     if (batch_concurrent(p, p->variant)) return batch_run_concurrent(p, fields, nsteps, src, rec, s);
-    const Variant var = variant_of(p->variant);
+    const Variant var = plan_variant(p, p->variant);
     // shots whose sources carry per-point scales use their formed amounts
     std::vector<stencil_source> srcs;
     if (src) {
@@ -2065,9 +2172,15 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
     }
     std::vector<ZView> views;
     ST_TRY(batch_prepare(p, fields, nsteps, src ? srcs.data() : nullptr, rec, var, views));
+    if (var.persistent) {
+        if (nsteps > INT_MAX) return fail(STENCIL_E_INVALID, "the persistent batched sweep takes at most 2^31 - 1 steps");
+        ST_TRY(prepare_persistent(p, var, p->hmap, p->nblocks, p->plist, p->poff));
+    }
     if (nsteps >= 2 && graphs_enabled()) {
         std::vector<int64_t> key = {nsteps, p->variant, (int64_t)(uintptr_t)p->views.buf.p, any_rec,
-                                    (int64_t)(uintptr_t)p->block_map.buf.p, (int64_t)(uintptr_t)p->ws,
+                                    (int64_t)(uintptr_t)p->block_map.buf.p, (int64_t)(uintptr_t)p->ws, p->pgrid,
+                                    (int64_t)(uintptr_t)p->bsync.p, barrier_polls(), (int64_t)(uintptr_t)p->plist.buf.p,
+                                    (int64_t)(uintptr_t)p->poff.buf.p,
                                     (int64_t)(uintptr_t)p->tbviews[0].buf.p, (int64_t)(uintptr_t)p->tbviews[1].buf.p};
         for (const ZView& v : views) {
             key.push_back((int64_t)(uintptr_t)v.u);
@@ -2111,6 +2224,7 @@ stencil_status stencil_batch_run(stencil_plan p, void** fields, int64_t nsteps, 
     }
     if (nsteps & 1)
         for (int sh = 0; sh < ns; sh++) std::swap(fields[3 * sh], fields[3 * sh + 1]);
+    if (var.persistent && nsteps > 0) ST_TRY(check_persistent(p, s));
     return STENCIL_OK;
 }
 
@@ -2589,6 +2703,10 @@ stencil_status stencil_variant_name(stencil_plan p, int variant, char* buf, size
                                   tile;
     } else if (batch_concurrent(p, variant)) {
         name = "shots_concurrent_" + std::to_string(kBranches);
+    } else if (batch_persistent(p, variant)) {
+        const Variant v = plan_variant(p, variant);
+        name = "persistent_zmarch_" + std::to_string(tile_tx(v.cfg)) + "x" + std::to_string(tile_ty(v.cfg)) + "_t" +
+               std::to_string(tile_threads(v.cfg)) + "_zc" + std::to_string(v.zc) + (kTileCfgs[v.cfg].nt ? "_nt" : "");
     } else if (p->ndim == 2 && variant > 0) {
         const Heat2dCfg& c = kHeat2dCfgs[variant - 1];
         name = "tb2d_t" + std::to_string(c.t) + "_" + std::to_string(c.tx) + "x" + std::to_string(c.ty);
@@ -2901,7 +3019,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
     int best = p->variant;
     float best_ms = 1e30f;
     stencil_status st = STENCIL_OK;
-    DevTable vt, bs, tvt;
+    DevTable vt, bs, tvt, pl, po;
     for (int var_i = p->batch ? 1 : 0; var_i < nvar && st == STENCIL_OK; var_i++) {
         if (batch_concurrent(p, var_i)) {
             float ms = 0;
@@ -2922,7 +3040,7 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             }
             continue;
         }
-        const Variant var = variant_of(var_i);
+        const Variant var = plan_variant(p, var_i);
         std::vector<ZView> views;
         std::vector<int> bst(1, 0);
         int64_t off = 0;
@@ -2946,12 +3064,14 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
         if (p->batch) {
             st = vt.upload(views.data(), sizeof(ZView) * views.size());
             int padded = 0;
+            std::vector<int> hm;
             if (st == STENCIL_OK) {
                 std::vector<int> nz;
                 for (const Layout* L : Ls) nz.push_back(L->g.n[0]);
-                st = build_block_map_impl(views, nz, p->radius, bs, padded);
+                st = build_block_map_impl(views, nz, p->radius, bs, padded, &hm);
             }
             bst.back() = padded;
+            if (st == STENCIL_OK && var.persistent) st = prepare_persistent(p, var, hm, padded, pl, po);
             if (st == STENCIL_OK && var.tb) {
                 std::vector<TBView> tv;
                 int64_t o2 = off;
@@ -2983,6 +3103,16 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
                                         p->w, s);
             if (var.tb && p->batch)
                 return tb2_batch(p->dtype, (const TBView*)tvt.buf.p, (const int*)bs.buf.p, bst.back(), p->w, 0, -1, -1, s);
+            if (var.persistent) {
+                // kPersistentTuneSteps steps in one launch, each reading the
+                // caller's levels and writing the scratch output (parity 0)
+                hipError_t e = launch_zero(p->bsync.p, kPersistentWords * sizeof(unsigned long long), s);
+                if (e != hipSuccess) return e;
+                return launch_zmarch_batch_persistent(p->radius, p->dtype, var.cfg, (const ZView*)vt.buf.p,
+                                                      (const int*)pl.buf.p, (const int*)po.buf.p, p->pgrid, p->w, 0,
+                                                      kPersistentTuneSteps, 0, 0, (unsigned long long*)p->bsync.p,
+                                                      barrier_polls(), s);
+            }
             if (var.tb) {
                 const Layout& L = p->L;
                 TBView t{};
@@ -3028,6 +3158,14 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
             break;
         }
         if (var.tb) ms *= 0.5f;   // one launch advances two steps
+        if (var.persistent) {
+            ms /= (float)kPersistentTuneSteps;
+            const stencil_status cs = check_persistent(p, s);
+            if (cs != STENCIL_OK) {
+                st = cs;
+                break;
+            }
+        }
         if (heat2d) ms /= (float)kHeat2dCfgs[var_i - 1].t;
         if (ms < best_ms) {
             best_ms = ms;

@@ -782,6 +782,117 @@ __global__ __launch_bounds__(BX* BY) void k_zmarch_batch(const ZView* __restrict
     zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, local, parity, arow, trow, lds);
 }
 
+// Batched shots in one persistent launch: steps t0 .. t1 - 1 of every shot.
+// The (shot, block) entries sit in 8 queues, one per XCD: queue x holds
+// list[qoff[x]] .. list[qoff[x + 1] - 1], the entries the host laid out for
+// XCD x, in map order.  Each step a workgroup takes entries one at a time
+// from its own XCD's queue (the hardware register XCC_ID names the XCD) by
+// an atomic ticket, and from the other queues in turn once that one is
+// empty, so the XCD's compute units run a moving window of neighbouring
+// tiles (their halo rows shared in the XCD's L2) and the work evens out as
+// the hardware dispatcher evens out one launch's workgroups.  The next
+// ticket is taken while the current entry runs.  Tickets count in
+// sync[2 + 8 p + x] for step parity p; workgroup 0 clears the other
+// parity's counters during a step, and the barrier after it orders the
+// clearing before their next use.
+// Between steps the grid meets at a barrier: arrivals count in sync[0]
+// (each workgroup adds one per step; the barrier after step t opens at
+// (t - t0 + 1) G), with an agent-scope release before the arrival and an
+// acquire after the opening, so that a step's stores from any XCD reach the
+// next step's loads on every other.  The wait is bounded: after spin_limit
+// polls, or once another workgroup has given up, a workgroup sets sync[1]
+// and leaves, and the host reports the error.  The host sizes the grid so
+// that all of it is resident at once.  pmask: step t runs with parity
+// t & pmask (0 for timing runs, which read the same levels every step and
+// write a scratch output).
+template <int R, typename T, int BX, int BY, int VY, int VX, bool NTH>
+__global__ __launch_bounds__(BX* BY) void k_zmarch_batch_persistent(const ZView* __restrict__ views,
+                                                                   const int* __restrict__ list,
+                                                                   const int* __restrict__ qoff, Coefs w, int t0,
+                                                                   int t1, int rec_on, int pmask,
+                                                                   unsigned long long* sync, int spin_limit) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    __shared__ int give_up, next_entry;
+    const int G = gridDim.x;
+    // this workgroup's XCD (bits 3:0 of hardware register 20, XCC_ID)
+    const int xcd = __builtin_amdgcn_s_getreg(0x1814) & 7;
+    int q = xcd, tried = 0;
+    unsigned long long* cnt = sync + 2;
+    // thread 0: the next entry of the step's queues, or -1 when all are empty
+    auto grab = [&](int par) -> int {
+        while (tried < 8) {
+            const unsigned long long k = atomicAdd(&cnt[8 * par + q], 1ull);
+            if (k < (unsigned long long)(qoff[q + 1] - qoff[q])) return qoff[q] + (int)k;
+            q = (q + 1) & 7;
+            tried++;
+        }
+        return -1;
+    };
+    for (int t = t0; t < t1; t++) {
+        const int par = t & 1;
+        const int trow = (rec_on && t >= 1) ? t - 1 : -1;
+        if (blockIdx.x == 0 && threadIdx.x < 8)
+            __hip_atomic_store(&cnt[8 * (par ^ 1) + threadIdx.x], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        q = xcd;
+        tried = 0;
+        if (threadIdx.x == 0) next_entry = grab(par);
+        __syncthreads();
+        int e = next_entry;
+        while (e >= 0) {
+            __syncthreads();   // every thread has read next_entry
+            if (threadIdx.x == 0) next_entry = grab(par);
+            const ZView v = views[list[2 * e]];
+            zmarch_tile<MODE_WAVE, R, T, BX, BY, VY, VX, NTH>(v, w, list[2 * e + 1], t & pmask, t, trow, lds);
+            __syncthreads();   // the next tile refills the LDS planes
+            e = next_entry;
+        }
+        if (t + 1 == t1) break;
+        // every wave's stores complete (in the L2), then one agent-scope
+        // release per workgroup: the L2 write-back covers all its waves'
+        // stores, and one per workgroup keeps the write-backs at each barrier
+        // to the number of workgroups
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);   // the write-back is done before the arrival below
+        }
+        if (threadIdx.x == 0) {
+            // a workgroup that is not the last to arrive polls, at most
+            // spin_limit times (so a zero limit makes the first arrival give up)
+            const unsigned long long open = (unsigned long long)(t - t0 + 1) * (unsigned long long)G;
+            const unsigned long long arrived = atomicAdd(&sync[0], 1ull) + 1ull;
+            bool stop = false;
+            if (arrived < open) {
+                // sparse polls (a sleep of about 0.5 us between them, the
+                // error flag every 64th) keep the waiting workgroups' coherent
+                // loads from crowding the memory channel of the count
+                for (int polls = 0;; polls++) {
+                    if (polls >= spin_limit ||
+                        ((polls & 63) == 0 && __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        stop = true;
+                        break;
+                    }
+                    if (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= open) break;
+                    __builtin_amdgcn_s_sleep(20);
+                }
+            }
+            if (stop) atomicOr(&sync[1], 1ull);
+            give_up = stop;
+        }
+        __syncthreads();
+        if (give_up) return;
+        // one acquire per workgroup: it invalidates the compute unit's L1,
+        // which the workgroup's waves share, and the L2 lines other XCDs may
+        // have written; the barrier orders it before every wave's next loads
+        if (threadIdx.x < 64) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);   // the invalidation is done before the barrier
+        }
+        __syncthreads();
+    }
+}
+
 // dynamic LDS above 64 KiB must be enabled per kernel once
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
@@ -852,6 +963,46 @@ static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bma
     return hipErrorInvalidValue;
 }
 
+
+template <typename T>
+static hipError_t zbp_kernel(int radius, int cfg, const void*& k, size_t& lds, int& threads) {
+    if (radius != 4 || cfg != kPersistentCfg) return hipErrorInvalidValue;
+    constexpr TileCfg c = kTileCfgs[kPersistentCfg];
+    lds = sizeof(LdsT<T>) * ZTile<4, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    threads = c.bx * c.by;
+    auto kf = k_zmarch_batch_persistent<4, T, c.bx, c.by, c.vy, c.vx, c.nt>;
+    static const hipError_t attr = allow_lds(kf, lds);
+    if (attr != hipSuccess) return attr;
+    k = reinterpret_cast<const void*>(kf);
+    return hipSuccess;
+}
+
+// workgroups of the persistent batched sweep one compute unit holds at once
+template <typename T>
+static hipError_t zbp_per_cu(int radius, int cfg, int& per_cu) {
+    const void* k = nullptr;
+    size_t lds = 0;
+    int threads = 0;
+    const hipError_t e = zbp_kernel<T>(radius, cfg, k, lds, threads);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds);
+}
+
+template <typename T>
+static hipError_t zbp_launch(int radius, int cfg, const ZView* views, const int* list, const int* qoff, int grid,
+                             const Coefs& w, int t0, int t1, int rec_on, int pmask, unsigned long long* sync,
+                             int spin_limit, hipStream_t s) {
+    constexpr TileCfg c = kTileCfgs[kPersistentCfg];
+    const void* k = nullptr;
+    size_t lds = 0;
+    int threads = 0;
+    const hipError_t e = zbp_kernel<T>(radius, cfg, k, lds, threads);
+    if (e != hipSuccess) return e;
+    if (grid <= 0 || t1 <= t0) return hipSuccess;
+    hipLaunchKernelGGL((k_zmarch_batch_persistent<4, T, c.bx, c.by, c.vy, c.vx, c.nt>), dim3((unsigned)grid),
+                       dim3(threads), lds, s, views, list, qoff, w, t0, t1, rec_on, pmask, sync, spin_limit);
+    return hipGetLastError();
+}
 
 // mode dispatch for one storage type and a set of modes
 template <typename T>

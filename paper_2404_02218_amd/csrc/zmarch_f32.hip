@@ -13,4 +13,14 @@ hipError_t zmarch_batch_f32(int radius, int cfg, const ZView* views, const int* 
     return zb_cfg<float>(radius, cfg, views, bmap, nblocks, w, parity, arow, trow, s);
 }
 
+hipError_t zmarch_batch_persistent_f32(int radius, int cfg, const ZView* views, const int* list, const int* off, int grid,
+                                      const Coefs& w, int t0, int t1, int rec_on, int pmask, unsigned long long* sync,
+                                      int spin_limit, hipStream_t s) {
+    return zbp_launch<float>(radius, cfg, views, list, off, grid, w, t0, t1, rec_on, pmask, sync, spin_limit, s);
+}
+
+hipError_t zmarch_batch_persistent_per_cu_f32(int radius, int cfg, int* per_cu) {
+    return zbp_per_cu<float>(radius, cfg, *per_cu);
+}
+
 }  // namespace stn

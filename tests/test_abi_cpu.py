@@ -217,13 +217,15 @@ def test_batch_plan_validation():
         S.BatchPlan([(10, 10, 10)], 2, S.second_derivative_weights(4))
     bp = S.BatchPlan([(10, 12, 14), (20, 9, 33)], 4, S.second_derivative_weights(8))
     assert len(bp.layouts) == 2
-    assert bp.variant_count() == 21
+    assert bp.variant_count() == 25
     assert bp.variant_name(17).startswith("tb2_")
-    assert bp.variant_name(20) == "shots_concurrent_4"
+    assert [bp.variant_name(v) for v in range(20, 24)] == [
+        f"persistent_zmarch_64x16_t256_zc{zc}_nt" for zc in (256, 128, 64, 32)]
+    assert bp.variant_name(24) == "shots_concurrent_4"
     # the concurrent variant runs the shots' own plans: no workspace until
     # one of them is tuned to the temporally blocked sweep
-    bp.variant = 20
-    assert bp.variant == 20
+    bp.variant = 24
+    assert bp.variant == 24
     assert list(bp.layouts[1].extents) == [28, 17, 41]
     with pytest.raises(S.StencilError):
         bp.variant = 0

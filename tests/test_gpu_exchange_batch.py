@@ -109,6 +109,8 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
     assert len(tb) == 3
     conc = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("shots_concurrent")]
     assert len(conc) == 1
+    pers = [v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("persistent_")]
+    assert len(pers) == 4
     fields, srcs, amps, recs, trs, ins = [], [], [], [], [], []
     for i, sh in enumerate(shapes):
         u0, um1, beta = wave_inputs(sh, seed=100 + i, dtype=dtype)
@@ -121,7 +123,7 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
         amps.append(torch_f64(np.random.default_rng(200 + i).standard_normal((steps, 1)), device))
         recs.append(np.array([[1, 2, 3], [s - 1 for s in sh]][: 1 + i % 2]))
         trs.append(torch.zeros((steps, len(recs[-1])), dtype=torch.float64, device=device))
-    for v in (1, 5, 9, *tb, *conc):
+    for v in (1, 5, 9, *tb, *pers, *conc):
         bp.variant = v
         for i in range(len(shapes)):
             for fld, a in zip(fields[i], ins[i]):
@@ -135,6 +137,42 @@ def test_batched_equals_sequential_bitwise(device, steps, dtype):
             assert np.array_equal(fields[i][0].interior(4), a), (v, i)
             assert np.array_equal(fields[i][1].interior(4), b), (v, i)
             assert np.array_equal(trs[i].cpu().numpy(), tr), (v, i)
+
+
+def test_persistent_batch_barrier_gives_up_and_reports(device, monkeypatch):
+    """The persistent batched sweep's grid barrier waits a bounded number of
+    polls.  Forced to zero from the host, the first workgroup to arrive gives
+    up, every other one leaves at its next barrier, the run reports the error
+    instead of returning fields, and a later run with the default bound gives
+    the sequential runs' bits again."""
+    import torch
+    shapes = [(20, 33, 45), (28, 28, 28)]
+    steps = 6
+    bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
+    v = next(v for v in range(bp.variant_count()) if bp.variant_name(v).startswith("persistent_"))
+    bp.variant = v
+    ins = [wave_inputs(sh, seed=300 + i) for i, sh in enumerate(shapes)]
+    fields = [[bp.field(i) for _ in range(3)] for i in range(len(shapes))]
+
+    def load():
+        for f, x in zip(fields, ins):
+            for fld, a in zip(f, x):
+                fld.load(W.embed(a, 4))
+
+    load()
+    monkeypatch.setenv("STENCIL_BARRIER_POLLS", "0")
+    with pytest.raises(S.StencilError, match="grid barrier"):
+        bp.run(fields, steps)
+    monkeypatch.delenv("STENCIL_BARRIER_POLLS")
+    fields = [[bp.field(i) for _ in range(3)] for i in range(len(shapes))]
+    load()
+    bp.run(fields, steps)
+    torch.cuda.synchronize()
+    for i, sh in enumerate(shapes):
+        plan = S.Plan(S.WAVE2, sh, 4, S.second_derivative_weights(8), halo=4)
+        a, b, _ = gpu_wave(plan, *ins[i], steps)
+        assert np.array_equal(fields[i][0].interior(4), a), i
+        assert np.array_equal(fields[i][1].interior(4), b), i
 
 
 def test_concurrent_batch_with_tuned_shot_plans(device, monkeypatch):

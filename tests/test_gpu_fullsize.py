@@ -163,25 +163,39 @@ def test_c3_full_size_temporal_blocking_equals_plain_sweep(device, dn):
         del got
 
 
-def test_c4_full_size_batched_equals_sequential(device):
+@pytest.mark.parametrize("variant", [None, "persistent_zmarch_64x16_t256_zc32_nt"])
+def test_c4_full_size_batched_equals_sequential(device, variant):
+    # the tuned batch variant from zero levels, and the persistent launch
+    # (grid barriers between steps) from random levels, so that every halo
+    # row a tile reads from a neighbour processed elsewhere carries data
     import torch
     B = W.batch_c4(nsteps=6)
     shapes = [s.shape for s in B.shots]
     bp = S.BatchPlan(shapes, 4, S.second_derivative_weights(8))
     fields, amps, recs, trs = [], [], [], []
+    gen = torch.Generator(device=device).manual_seed(7)
     for i, sh in enumerate(B.shots):
         g = [bp.field(i) for _ in range(3)]
         g[2].load(W.embed(W.round_to_storage(sh.beta, "f32"), 4))
+        if variant is not None:
+            for k in (0, 1):
+                g[k].view[4:-4, 4:-4, 4:-4] = torch.rand(sh.shape, generator=gen, device=device) - 0.5
         fields.append(g)
         amps.append(torch_f64(sh.src_amp, device))
         recs.append(np.array([[8, sh.shape[1] // 2, sh.shape[2] // 2]]))
         trs.append(torch.zeros((6, 1), dtype=torch.float64, device=device))
-    bp.tune(fields, reps=1)
+    init = [[f[k].storage.clone() for k in (0, 1)] for f in fields]
+    if variant is None:
+        bp.tune(fields, reps=1)
+    else:
+        bp.variant = next(v for v in range(bp.variant_count()) if bp.variant_name(v) == variant)
     bp.run(fields, 6, [sh.src for sh in B.shots], amps, recs, trs)
     torch.cuda.synchronize()
     for i, sh in enumerate(B.shots):
         p = S.Plan(S.WAVE2, sh.shape, 4, S.second_derivative_weights(8), halo=4)
         g = [p.field() for _ in range(3)]
+        g[0].storage.copy_(init[i][0])
+        g[1].storage.copy_(init[i][1])
         g[2].storage.copy_(fields[i][2].storage)
         t = torch.zeros((6, 1), dtype=torch.float64, device=device)
         p.run(g, 6, src=sh.src, src_amp=amps[i], rec=recs[i], rec_trace=t)
