@@ -298,12 +298,23 @@ stencil_status stencil_batch_layout(stencil_plan batch, int shot, int64_t* exten
                                     int64_t* offset, int64_t* bytes);
 
 /* nsteps sweeps of every shot (Section 6.1 wave sweep per shot, as in
- * stencil_run): one launch per step (two steps for the temporally blocked
- * variant) covers the tiles of all shots, and the launches are captured
- * into one HIP graph.  fields[3*s + {0,1,2}] = shot s's {u_n, u_prev, beta},
- * permuted per shot as in stencil_run.  src / rec: arrays of nshots entries,
- * or NULL.  The temporally blocked variant needs a workspace as
- * stencil_run does (one field pair per shot). */
+ * stencil_run), captured into one HIP graph.  By variant:
+ *   - fused (zmarch_*, tb2_*): one launch per step (two steps for the
+ *     temporally blocked form) covers the tiles of all shots;
+ *   - persistent_zmarch_*: one launch runs every step over per-XCD queues of
+ *     the shots' tiles, with a grid barrier between steps.  Its grid is as
+ *     many workgroups as the GPU holds at once; a barrier wait is bounded
+ *     (STENCIL_BARRIER_POLLS polls if set, else 2^20), and a wait that gives
+ *     up (the grid was not all resident, e.g. beside other work on the GPU)
+ *     fails the call with STENCIL_E_DEVICE and leaves the fields invalid.
+ *     This variant synchronises `stream` before it returns, to read that
+ *     flag;
+ *   - shots_concurrent_4: every shot's own tuned run, on four branches of the
+ *     graph.
+ * fields[3*s + {0,1,2}] = shot s's {u_n, u_prev, beta}, permuted per shot as
+ * in stencil_run.  src / rec: arrays of nshots entries, or NULL.  The
+ * temporally blocked variant needs a workspace as stencil_run does (one
+ * field pair per shot). */
 stencil_status stencil_batch_run(stencil_plan batch, void** fields, int64_t nsteps,
                                  const stencil_source* src, const stencil_receivers* rec, void* stream);
 
