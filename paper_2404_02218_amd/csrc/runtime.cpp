@@ -2294,6 +2294,9 @@ struct SegLevels {
 static stencil_status forward_ckpt_impl(stencil_plan p, void** fields, int64_t nsteps, int64_t k,
                                         const stencil_source* src, const stencil_receivers* rec, void* ws,
                                         const AdjLayout& A, hipStream_t s) {
+    // until this forward completes, no workspace holds a last segment's
+    // second differences this plan can vouch for
+    p->last_seg_ws = nullptr;
     const Variant var = adjoint_variant(p);
     ST_TRY(build_points(p->L, src ? src->n : 0, src ? src->pos : nullptr, var.cfg, p->src));
     ST_TRY(build_points(p->L, rec ? rec->n : 0, rec ? rec->pos : nullptr, -1, p->rec));
