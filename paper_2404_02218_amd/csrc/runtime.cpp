@@ -3074,7 +3074,9 @@ stencil_status stencil_tune(stencil_plan p, void* const* fields, int reps, void*
                 st = build_block_map_impl(views, nz, p->radius, bs, padded, &hm);
             }
             bst.back() = padded;
-            if (st == STENCIL_OK && var.persistent) st = prepare_persistent(p, var, hm, padded, pl, po);
+            // a persistent variant the device cannot hold at once is skipped
+            if (st == STENCIL_OK && var.persistent && prepare_persistent(p, var, hm, padded, pl, po) != STENCIL_OK)
+                continue;
             if (st == STENCIL_OK && var.tb) {
                 std::vector<TBView> tv;
                 int64_t o2 = off;
