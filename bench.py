@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (else tune)")
+    ap.add_argument("--variant", default="-1",
+                    help="force a kernel variant, by number or by name (else tune)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage dtype of the headline leg (profiling of the 16-bit kernels)")
     ap.add_argument("--leg", default=None,
@@ -156,6 +157,20 @@ def launch_model(vname, nsteps, es, storage):
     return False, nsteps, 4 * es, f"k_zmarch<wave, r=4, {storage}>"
 
 
+def resolve_variant(plan, spec) -> int:
+    """The plan's variant number for `spec`: a number, or a variant name
+    (names stay the same when variants are added); -1 for none."""
+    spec = str(spec)
+    try:
+        return int(spec)
+    except ValueError:
+        pass
+    names = {plan.variant_name(v): v for v in range(plan.variant_count())}
+    if spec not in names:
+        raise SystemExit(f"unknown variant {spec!r}; this plan has {sorted(names)}")
+    return names[spec]
+
+
 def wave_setup(S, W, n, nsteps, dtype, variant):
     import torch
     P = W.wave3d_c3(n=n, nsteps=nsteps)
@@ -164,6 +179,7 @@ def wave_setup(S, W, n, nsteps, dtype, variant):
     f = [plan.field() for _ in range(3)]
     f[2].load(W.embed(W.round_to_storage(P.beta, dn), 4))
     amp = torch.from_numpy(P.src_amp).cuda()
+    variant = resolve_variant(plan, variant)
     if variant >= 0:
         plan.variant = variant
     else:
@@ -397,6 +413,7 @@ def bench_heat3d(S, W, steps, variant=-1, nsteps=50):
     hp = S.Plan(S.HEAT, H.shape, 2, S.heat_weights(4, H.alpha), halo=2)
     hf = [hp.field() for _ in range(2)]
     hf[0].load(W.embed(W.round_to_storage(H.u0, "f32"), 2))
+    variant = resolve_variant(hp, variant)
     if variant >= 0:
         hp.variant = variant
     else:
@@ -436,6 +453,7 @@ def bench_pw(S, W, steps, n=512, variant=-1):
     for f in ins:
         f.view[1:-1, 1:-1, 1:-1] = torch.rand(shape, generator=gen, device="cuda") - 0.5
     outs = [prog.field() for _ in range(3)]
+    variant = resolve_variant(prog, variant)
     # the compiled forms (the generic kernel, variant 1, is a cross-check):
     # 64 x 16 tiles, the tight ring, 64 x 32 tiles; the fastest is reported
     per_variant = {}

@@ -141,6 +141,7 @@ inline constexpr TileCfg kTileCfgs[] = {
     {16, 16, 1, 4, true},   // 64 x 16 tile, 256 threads, streaming hints
     {8, 32, 1, 8, true},    // 64 x 32 tile, 256 threads, 8 points per lane, streaming hints
     {16, 16, 1, 4, false},  // 64 x 16 tile, 256 threads
+    {16, 16, 1, 8, true},   // 128 x 16 tile, 256 threads, 8 points per lane, streaming hints
 };
 inline constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 // the tile shape of the persistent batched sweep (64 x 16, streaming hints)

@@ -921,6 +921,7 @@ static hipError_t zm_cfg(int cfg, const ZView& v, const Coefs& w, int parity, in
         case 1: return zm_launch<MODE, R, T, 1>(v, w, parity, arow, trow, s);
         case 2: return zm_launch<MODE, R, T, 2>(v, w, parity, arow, trow, s);
         case 3: return zm_launch<MODE, R, T, 3>(v, w, parity, arow, trow, s);
+        case 4: return zm_launch<MODE, R, T, 4>(v, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }
@@ -959,6 +960,7 @@ static hipError_t zb_cfg(int radius, int cfg, const ZView* views, const int* bma
         case 1: return zb_launch<4, T, 1>(views, bmap, nblocks, w, parity, arow, trow, s);
         case 2: return zb_launch<4, T, 2>(views, bmap, nblocks, w, parity, arow, trow, s);
         case 3: return zb_launch<4, T, 3>(views, bmap, nblocks, w, parity, arow, trow, s);
+        case 4: return zb_launch<4, T, 4>(views, bmap, nblocks, w, parity, arow, trow, s);
     }
     return hipErrorInvalidValue;
 }

@@ -146,14 +146,15 @@ def test_product_weights_equal_oracle_derivation():
 def test_variants_are_listed():
     p = S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8))
     n = p.variant_count()
-    assert n == 20   # point, 16 z-marching, 3 temporally blocked
+    assert n == 24   # point, 20 z-marching (5 tile shapes x 4 z-chunks), 3 temporally blocked
     names = [p.variant_name(v) for v in range(n)]
     assert names[0] == "point" and len(set(names)) == n
-    assert [x for x in names if x.startswith("tb2_")] == names[17:]
+    assert [x for x in names if x.startswith("tb2_")] == names[21:]
+    assert "zmarch_128x16_t256_zc128_p8_nt" in names
     # temporal blocking covers the radius-4 wave with the zero halo only
-    assert S.Plan(S.WAVE2, (64, 64, 64), 2, S.second_derivative_weights(4)).variant_count() == 17
+    assert S.Plan(S.WAVE2, (64, 64, 64), 2, S.second_derivative_weights(4)).variant_count() == 21
     assert S.Plan(S.WAVE2, (64, 64, 64), 4, S.second_derivative_weights(8),
-                  bc=S.BC_PERIODIC).variant_count() == 17
+                  bc=S.BC_PERIODIC).variant_count() == 21
     # 2D heat (FP32, zero halo): the point kernel and four multi-step kernels
     p2 = S.Plan(S.HEAT, (64, 64), 1, S.heat_weights(2, 0.2))
     assert [p2.variant_name(v) for v in range(p2.variant_count())] == [
@@ -217,15 +218,15 @@ def test_batch_plan_validation():
         S.BatchPlan([(10, 10, 10)], 2, S.second_derivative_weights(4))
     bp = S.BatchPlan([(10, 12, 14), (20, 9, 33)], 4, S.second_derivative_weights(8))
     assert len(bp.layouts) == 2
-    assert bp.variant_count() == 25
-    assert bp.variant_name(17).startswith("tb2_")
-    assert [bp.variant_name(v) for v in range(20, 24)] == [
+    assert bp.variant_count() == 29
+    assert bp.variant_name(21).startswith("tb2_")
+    assert [bp.variant_name(v) for v in range(24, 28)] == [
         f"persistent_zmarch_64x16_t256_zc{zc}_nt" for zc in (256, 128, 64, 32)]
-    assert bp.variant_name(24) == "shots_concurrent_4"
+    assert bp.variant_name(28) == "shots_concurrent_4"
     # the concurrent variant runs the shots' own plans: no workspace until
     # one of them is tuned to the temporally blocked sweep
-    bp.variant = 24
-    assert bp.variant == 24
+    bp.variant = 28
+    assert bp.variant == 28
     assert list(bp.layouts[1].extents) == [28, 17, 41]
     with pytest.raises(S.StencilError):
         bp.variant = 0
