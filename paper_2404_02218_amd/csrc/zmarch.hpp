@@ -128,48 +128,54 @@ struct ZTile {
 // widened per read, one shift or mask per value; FP16 values stay 16-bit in
 // registers too and enter the arithmetic through the mixed-precision FMA.
 // Values pass through LDS unchanged either way.
-template <typename T>
-inline constexpr bool kLds16 = std::is_same<T, bf16>::value || std::is_same<T, f16>::value;
+//
+// BF16 tiles with 8 points per lane keep FP32 planes instead and widen each
+// value once, as it enters LDS: at that shape two workgroups share a compute
+// unit either way, and widening per read cost more issue slots than the
+// planes' extra LDS bytes.
+template <typename T, int VX>
+inline constexpr bool kLds16 =
+    std::is_same<T, f16>::value || (std::is_same<T, bf16>::value && VX != 8);
 // FP16: the z-queue, the taps and u_prev and beta stay in the storage type
 template <typename T>
 inline constexpr bool kMix = std::is_same<T, f16>::value;
 template <typename T>
 using QGroup = typename std::conditional<kMix<T>, u2v, float4>::type;
-template <typename T>
-using LdsT = typename std::conditional<kLds16<T>, T, float>::type;
-template <typename T>
-__device__ __forceinline__ float4 lds_get4(const LdsT<T>* p) {
-    if constexpr (kLds16<T>) return widen4<T>(*reinterpret_cast<const u2v*>(p));
+template <typename T, int VX>
+using LdsT = typename std::conditional<kLds16<T, VX>, T, float>::type;
+template <typename T, int VX>
+__device__ __forceinline__ float4 lds_get4(const LdsT<T, VX>* p) {
+    if constexpr (kLds16<T, VX>) return widen4<T>(*reinterpret_cast<const u2v*>(p));
     else return *reinterpret_cast<const float4*>(p);
 }
-template <typename T>
-__device__ __forceinline__ void lds_put4_raw(LdsT<T>* p, typename RawGroup<T>::type r) {
-    if constexpr (kLds16<T>) *reinterpret_cast<u2v*>(p) = r;
+template <typename T, int VX>
+__device__ __forceinline__ void lds_put4_raw(LdsT<T, VX>* p, typename RawGroup<T>::type r) {
+    if constexpr (kLds16<T, VX>) *reinterpret_cast<u2v*>(p) = r;
     else *reinterpret_cast<float4*>(p) = widen4<T>(r);
 }
 // a group of the z-queue into an LDS plane
-template <typename T>
-__device__ __forceinline__ void lds_put_q(LdsT<T>* p, const QGroup<T>& g);
+template <typename T, int VX>
+__device__ __forceinline__ void lds_put_q(LdsT<T, VX>* p, const QGroup<T>& g);
 // a group of 4 values that came from storage of type T (exact in T)
-template <typename T>
-__device__ __forceinline__ void lds_put4(LdsT<T>* p, float4 v) {
-    if constexpr (kLds16<T>) {
+template <typename T, int VX>
+__device__ __forceinline__ void lds_put4(LdsT<T, VX>* p, float4 v) {
+    if constexpr (kLds16<T, VX>) {
         const u2v r = {Storage<T>::pack2(v.x, v.y), Storage<T>::pack2(v.z, v.w)};
         *reinterpret_cast<u2v*>(p) = r;
     } else {
         *reinterpret_cast<float4*>(p) = v;
     }
 }
-template <typename T>
-__device__ __forceinline__ void lds_put_q(LdsT<T>* p, const QGroup<T>& g) {
+template <typename T, int VX>
+__device__ __forceinline__ void lds_put_q(LdsT<T, VX>* p, const QGroup<T>& g) {
     if constexpr (kMix<T>) *reinterpret_cast<u2v*>(p) = g;
-    else lds_put4<T>(p, g);
+    else lds_put4<T, VX>(p, g);
 }
 // a group of an LDS plane in the z-queue's form
-template <typename T>
-__device__ __forceinline__ QGroup<T> lds_get_q(const LdsT<T>* p) {
+template <typename T, int VX>
+__device__ __forceinline__ QGroup<T> lds_get_q(const LdsT<T, VX>* p) {
     if constexpr (kMix<T>) return *reinterpret_cast<const u2v*>(p);
-    else return lds_get4<T>(p);
+    else return lds_get4<T, VX>(p);
 }
 
 // Each thread owns VX consecutive x points (VX = 4 or 8) in VY consecutive
@@ -195,7 +201,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // same operations on every path and never wait for the stores
     constexpr bool DEFER = !ADJ && MODE != MODE_WAVE_D;
     using S = Storage<T>;
-    using LT = LdsT<T>;
+    using LT = LdsT<T, VX>;
     LT* const ldsT = reinterpret_cast<LT*>(lds);
 
     const int tid = threadIdx.x;
@@ -275,7 +281,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         LT* L = ldsT + ((p - zb) % NSLOT) * PLANE;
 #pragma unroll
         for (int m = 0; m < NH; m++)
-            if (hon[m]) lds_put4_raw<T>(&L[hlds[m]], load4_raw<T, false>(U + (int64_t)p * sz + hoff[m]));
+            if (hon[m]) lds_put4_raw<T, VX>(&L[hlds[m]], load4_raw<T, false>(U + (int64_t)p * sz + hoff[m]));
     }
     // loads in flight across a plane's compute stay in the storage type
     using Raw = typename RawGroup<T>::type;
@@ -306,7 +312,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
     // the FP32 form's; the second plane brings the bytes in flight back up
     // (512^3 BF16: 246 -> 210 us per sweep).  Other shapes and FP32 gain
     // nothing or lose, and keep distance 1.
-    constexpr bool PD2 = DEFER && kLds16<T> && VX == 8;
+    constexpr bool PD2 = DEFER && sizeof(T) == 2 && VX == 8;
     Raw pq[VY][NV], pp[VY][NV], pb[VY][NV], phal[NH];
     if constexpr (PD2) {
         const int64_t z1 = (int64_t)min(zb + 1, ze - 1) * sz;
@@ -409,12 +415,12 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
         for (int j = 0; j < VY; j++)
 #pragma unroll
             for (int c = 0; c < NV; c++)
-                lds_put_q<T>(&L[(R + ty * VY + j) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
+                lds_put_q<T, VX>(&L[(R + ty * VY + j) * LDX + 4 + VX * tx + 4 * c], qi(R)[j][c]);
         if (z + R < ze) {
             LT* H = ldsT + hslot * PLANE;
 #pragma unroll
             for (int m = 0; m < NH; m++)
-                if (hon[m]) lds_put4_raw<T>(&H[hlds[m]], hal[m]);
+                if (hon[m]) lds_put4_raw<T, VX>(&H[hlds[m]], hal[m]);
         }
 
         const bool more = z + 1 < ze;
@@ -486,7 +492,7 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
                 if (q2 >= R && q2 < R + VY)
                     yr[q2][c] = qi(R)[q2 - R][c];
                 else
-                    yr[q2][c] = lds_get_q<T>(L + (row0 - R + q2) * LDX + 4 + VX * tx + 4 * c);
+                    yr[q2][c] = lds_get_q<T, VX>(L + (row0 - R + q2) * LDX + 4 + VX * tx + 4 * c);
             }
 #pragma unroll
         for (int j = 0; j < VY; j++) {
@@ -536,8 +542,8 @@ __device__ __forceinline__ void zmarch_tile(const ZView& v, const Coefs& w, int 
             // x taps: 4 left of the thread's points, its own VX, 4 right
             float xv[VX + 8];
             {
-                const float4 xl = lds_get4<T>(Lr);
-                const float4 xr = lds_get4<T>(Lr + 4 + VX);
+                const float4 xl = lds_get4<T, VX>(Lr);
+                const float4 xr = lds_get4<T, VX>(Lr + 4 + VX);
                 xv[0] = xl.x;
                 xv[1] = xl.y;
                 xv[2] = xl.z;
@@ -904,7 +910,7 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 template <int MODE, int R, typename T, int C>
 static hipError_t zm_launch(const ZView& v, const Coefs& w, int parity, int arow, int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(LdsT<T>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(LdsT<T, c.vx>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     const int64_t nb = zmarch_blocks(v);
     if (nb == 0) return hipSuccess;
     auto k = k_zmarch<MODE, R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
@@ -942,7 +948,7 @@ template <int R, typename T, int C>
 static hipError_t zb_launch(const ZView* views, const int* bmap, int nblocks, const Coefs& w, int parity, int arow,
                             int trow, hipStream_t s) {
     constexpr TileCfg c = kTileCfgs[C];
-    constexpr size_t lds = sizeof(LdsT<T>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    constexpr size_t lds = sizeof(LdsT<T, c.vx>) * ZTile<R, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     if (nblocks == 0) return hipSuccess;
     auto k = k_zmarch_batch<R, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(k, lds);
@@ -970,7 +976,7 @@ template <typename T>
 static hipError_t zbp_kernel(int radius, int cfg, const void*& k, size_t& lds, int& threads) {
     if (radius != 4 || cfg != kPersistentCfg) return hipErrorInvalidValue;
     constexpr TileCfg c = kTileCfgs[kPersistentCfg];
-    lds = sizeof(LdsT<T>) * ZTile<4, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
+    lds = sizeof(LdsT<T, c.vx>) * ZTile<4, c.bx, c.by, c.vy, c.vx>::LDS_FLOATS;
     threads = c.bx * c.by;
     auto kf = k_zmarch_batch_persistent<4, T, c.bx, c.by, c.vy, c.vx, c.nt>;
     static const hipError_t attr = allow_lds(kf, lds);
