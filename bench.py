@@ -44,11 +44,13 @@ METRIC = "GPts/s + % of HBM peak, 3D so-8 wave; batched & adjoint vs plain, same
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 CSRC = os.path.join(ROOT, "paper_2404_02218_amd", "csrc")
 # the stored traffic is tied to the sources the headline's kernels compile
-# from: the translation units of the plain and temporally blocked FP32 sweeps
-# and every header they include (the host runtime and the other kernels do
-# not change what these kernels move)
+# from: the translation units of the plain and temporally blocked FP32 sweeps,
+# every header they include and the build script that holds their compiler
+# flags (the host runtime and the other kernels do not change what these
+# kernels move)
 KERNEL_SOURCES = [os.path.join(CSRC, f) for f in
-                  ("zmarch_tb.hip", "zmarch_f32.hip", "zmarch_tb.hpp", "zmarch.hpp", "kernels.hpp", "device.hpp")]
+                  ("zmarch_tb.hip", "zmarch_f32.hip", "zmarch_tb.hpp", "zmarch.hpp", "kernels.hpp", "device.hpp")] + \
+                 [os.path.join(ROOT, "paper_2404_02218_amd", "build.py")]
 
 
 def log(*a):
